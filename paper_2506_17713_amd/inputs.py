@@ -1,0 +1,271 @@
+"""Seeded synthetic inputs and workload descriptions.
+
+This module feeds the same bytes to the GPU library and to the CPU oracle.  It
+holds no arithmetic of the method itself -- no equilibrium, force, collision or
+streaming -- only geometry, initial density fields, noise and the parameter
+sets of the workloads.
+
+Arrays are in (z, y, x) order with x fastest; a D2Q9 domain has nz = 1.
+
+Initial fields follow the paper's tanh interface profile (Sec. 3.1, Eq. 18),
+read as rho = (rho_in + rho_out)/2 - (rho_in - rho_out)/2 tanh(2 (d - r) / w):
+the printed form subtracts the two halves and would give zero in the vapour.
+
+Porous media stand in for the Digital Rocks sphere packs the paper uses
+(Sec. 3.4): periodic Boolean models of overlapping spheres with uniformly
+distributed radii; a voxel is solid if its centre lies inside a sphere
+(minimum-image distance).  The number of spheres follows the Boolean-model
+porosity phi = exp(-n E[V_sphere] / V).
+"""
+from __future__ import annotations
+
+import json
+import math
+from dataclasses import dataclass, field, replace
+from pathlib import Path
+
+import numpy as np
+
+_COEX = Path(__file__).resolve().parents[1] / "tests" / "golden" / "cs_coexistence.json"
+
+
+def load_coexistence() -> dict:
+    """Carnahan-Starling (a=1, b=4, R=1) critical temperature, Maxwell
+    coexistence densities and the calibrated Zhang-Chen weight A per reduced
+    temperature, as written by tests/golden/make_cs_coexistence.py."""
+    with open(_COEX) as fh:
+        return json.load(fh)
+
+
+# --------------------------------------------------------------------------
+# Workload description (plain numbers; marshalled by each side separately).
+# --------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    lattice: str                      # "D2Q9" or "D3Q19"
+    shape: tuple                      # (nz, ny, nx)
+    nc: int = 1
+    collision: str = "BGK"            # "BGK" or "MRT"
+    storage: str = "F32"              # "F64", "F32", "F16DEV", "BF16DEV"
+    tau: tuple = (1.0, 1.0)
+    mrt_s: tuple | None = None        # explicit rates per component, else defaults
+    psi_kind: tuple = ("CS", "CS")    # "CS" (Carnahan-Starling EOS) or "DENSITY"
+    eos_a: tuple = (1.0, 1.0)
+    eos_b: tuple = (4.0, 4.0)
+    eos_R: tuple = (1.0, 1.0)
+    eos_T: tuple = (0.0, 0.0)         # absolute temperature
+    alpha: tuple = (1.0, 1.0)
+    A: tuple = (0.0, 0.0)
+    g: tuple = ((-1.0, 0.0), (0.0, -1.0))
+    body: tuple = (0.0, 0.0, 0.0)     # body acceleration
+    wet_mode: tuple = ("PHI", "PHI")
+    wet: tuple = (1.0, 1.0)           # uniform phi or drho
+    rho_min: tuple = (0.0, 0.0)
+    rho_max: tuple = (1e30, 1e30)
+    common_velocity: bool = True
+    steps: int = 100
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def shape_xyz(self):
+        nz, ny, nx = self.shape
+        return nx, ny, nz
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.shape))
+
+    @property
+    def q(self) -> int:
+        return 9 if self.lattice == "D2Q9" else 19
+
+    def mrt_rates(self, k: int) -> tuple:
+        """Relaxation rate of each moment row (rows in the order of the
+        Lallemand-Luo D2Q9 / d'Humieres D3Q19 bases).  Defaults: 1/tau on the
+        conserved and stress rows, 1.0 on every other row."""
+        if self.mrt_s is not None:
+            return tuple(self.mrt_s[k])
+        sv = 1.0 / self.tau[k]
+        if self.lattice == "D2Q9":
+            # rho, e, eps, jx, qx, jy, qy, pxx, pxy
+            return (sv, 1.0, 1.0, sv, 1.0, sv, 1.0, sv, sv)
+        # rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy, pyz, pxz, mx, my, mz
+        r = [1.0] * 19
+        for i in (0, 3, 5, 7, 9, 11, 13, 14, 15):
+            r[i] = sv
+        return tuple(r)
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+# --------------------------------------------------------------------------
+# Geometry and initial-field generators.
+# --------------------------------------------------------------------------
+def grid(shape):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return x.astype(np.float64), y.astype(np.float64), z.astype(np.float64)
+
+
+def tanh_profile(d: np.ndarray, r: float, w: float, rho_in: float, rho_out: float) -> np.ndarray:
+    return 0.5 * (rho_in + rho_out) - 0.5 * (rho_in - rho_out) * np.tanh(2.0 * (d - r) / w)
+
+
+def droplet(shape, center_xyz, r, w, rho_in, rho_out) -> np.ndarray:
+    x, y, z = grid(shape)
+    cx, cy, cz = center_xyz
+    d = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)
+    return tanh_profile(d, r, w, rho_in, rho_out)
+
+
+def slab(shape, axis: str, lo: float, hi: float, w: float, rho_in, rho_out) -> np.ndarray:
+    """rho_in on lo <= c < hi along the axis (periodic distance to the faces)."""
+    x, y, z = grid(shape)
+    c = {"x": x, "y": y, "z": z}[axis]
+    L = {"x": shape[2], "y": shape[1], "z": shape[0]}[axis]
+    mid, half = 0.5 * (lo + hi - 1), 0.5 * (hi - lo)
+    dc = np.abs(c - mid)
+    dc = np.minimum(dc, L - dc)
+    return tanh_profile(dc, half, w, rho_in, rho_out)
+
+
+def uniform_noise(shape, amp: float, seed: int) -> np.ndarray:
+    """Additive U(-amp, amp) noise from numpy's PCG64 stream."""
+    return np.random.default_rng(seed).uniform(-amp, amp, size=shape)
+
+
+def walls(shape, axis: str, planes) -> np.ndarray:
+    solid = np.zeros(shape, dtype=np.uint8)
+    for p in planes:
+        if axis == "z":
+            solid[p, :, :] = 1
+        elif axis == "y":
+            solid[:, p, :] = 1
+        else:
+            solid[:, :, p] = 1
+    return solid
+
+
+def sphere_pack(shape, radii=(8.0, 16.0), porosity=0.35, seed=0, count=None) -> np.ndarray:
+    """Periodic Boolean model of overlapping spheres (uint8 mask, 1 = solid)."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    a, b = radii
+    er3 = (b ** 4 - a ** 4) / (4.0 * (b - a)) if b > a else a ** 3
+    if count is None:
+        count = int(round(-math.log(porosity) * nx * ny * nz / (4.0 / 3.0 * math.pi * er3)))
+    centers = rng.uniform(0.0, 1.0, size=(count, 3)) * np.array([nx, ny, nz])
+    rad = rng.uniform(a, b, size=count)
+    solid = np.zeros(shape, dtype=np.uint8)
+    for (cx, cy, cz), r in zip(centers, rad):
+        ri = int(math.ceil(r)) + 1
+        xs = np.arange(int(math.floor(cx)) - ri, int(math.floor(cx)) + ri + 2)
+        ys = np.arange(int(math.floor(cy)) - ri, int(math.floor(cy)) + ri + 2)
+        zs = np.arange(int(math.floor(cz)) - ri, int(math.floor(cz)) + ri + 2)
+        dx2 = (xs - cx) ** 2
+        dy2 = (ys - cy) ** 2
+        dz2 = (zs - cz) ** 2
+        inside = (dz2[:, None, None] + dy2[None, :, None] + dx2[None, None, :]) <= r * r
+        iz, iy, ix = np.nonzero(inside)
+        solid[zs[iz] % nz, ys[iy] % ny, xs[ix] % nx] = 1
+    return solid
+
+
+# --------------------------------------------------------------------------
+# Named workloads.
+# --------------------------------------------------------------------------
+def _cs(tr: float):
+    c = load_coexistence()
+    key = f"{tr:.1f}"
+    e = c["CS"][key]
+    return c["CS"]["Tc"] * tr, e["rho_v"], e["rho_l"], e["A"]
+
+
+def droplet_2d(n=128, steps=2000, storage="F64", r=20.0, w=5.0, tr=0.7, seed=0, noise=1e-4,
+               collision="BGK"):
+    """D2Q9 single-component Carnahan-Starling droplet in its vapour, periodic,
+    BGK tau = 1 (the small double-precision case)."""
+    T, rv, rl, A = _cs(tr)
+    shape = (1, n, n)
+    wl = Workload("droplet2d", "D2Q9", shape, storage=storage, collision=collision,
+                  tau=(1.0, 1.0), eos_T=(T, T), A=(A, A), rho_min=(rv, rv), rho_max=(rl, rl),
+                  steps=steps)
+    rho = droplet(shape, (n / 2, n / 2, 0.0), r, w, rl, rv) + uniform_noise(shape, noise, seed)
+    solid = np.zeros(shape, dtype=np.uint8)
+    return wl, solid, rho[None]
+
+
+def sessile_3d(n=256, steps=20000, storage="F32", r=30.0, w=5.0, tr=0.8, wet_mode="PHI",
+               wet=1.0, collision="MRT", nxy=None, center=None):
+    """D3Q19 Carnahan-Starling droplet resting on a solid wall at z = 0 (and a
+    second wall at z = nz-1); x and y periodic."""
+    T, rv, rl, A = _cs(tr)
+    nx = ny = nxy or n
+    shape = (n, ny, nx)
+    wl = Workload("sessile3d", "D3Q19", shape, storage=storage, collision=collision,
+                  tau=(1.0, 1.0), eos_T=(T, T), A=(A, A), wet_mode=(wet_mode, wet_mode),
+                  wet=(wet, wet), rho_min=(rv, rv), rho_max=(rl, rl), steps=steps)
+    solid = walls(shape, "z", (0, n - 1))
+    c = center or (nx / 2, ny / 2, r + 1.0)
+    rho = droplet(shape, c, r, w, rl, rv)
+    return wl, solid, rho[None]
+
+
+def two_component_pack(n=400, steps=100, storage="F32", seed=0, porosity=0.35, radii=(8.0, 16.0),
+                       rho_major=1.0, minor_frac=0.03, phi_w=1.2, drho_nw=0.1, shape=None,
+                       solid=None):
+    """D3Q19 two-component Shan-Chen (psi = rho) in a periodic sphere pack.
+    Component 0 is non-wetting and fills pores with x < 0.4 nx; component 1 is
+    wetting.  g_kk = -0.027, g_12 = 0.57, A = 0 (Sec. 3.3.2); body force 1e-6
+    along x; each component is present at minor_frac of rho_major where the
+    other dominates.  With G_i = w_i / c_s^2, rho_major = 1 makes 3 % the
+    equilibrium solubility of these strengths (the fraction Sec. 3.3.2 uses);
+    the wall densities are limited to [0, 1.1 rho_major]."""
+    shape = shape or (n, n, n)
+    nz, ny, nx = shape
+    if solid is None:
+        solid = sphere_pack(shape, radii, porosity, seed)
+    minor = minor_frac * rho_major
+    front = slab(shape, "x", 0, int(round(0.4 * nx)), 3.0, 1.0, 0.0)  # tanh edges, width 3
+    rho = np.empty((2,) + tuple(shape))
+    rho[0] = minor + (rho_major - minor) * front
+    rho[1] = minor + (rho_major - minor) * (1.0 - front)
+    g = ((-0.027, 0.57), (0.57, -0.027))
+    wl = Workload("twocomp_pack", "D3Q19", tuple(shape), nc=2, storage=storage, collision="BGK",
+                  tau=(1.0, 1.0), psi_kind=("DENSITY", "DENSITY"), A=(0.0, 0.0), g=g,
+                  body=(1e-6, 0.0, 0.0), wet_mode=("DRHO", "PHI"), wet=(drho_nw, phi_w),
+                  rho_min=(0.0, 0.0), rho_max=(1.1 * rho_major, 1.1 * rho_major), steps=steps)
+    return wl, solid, rho
+
+
+def adjoint_pack(n=128, steps=1000, storage="F32", seed=1, porosity=0.4, radii=(6.0, 14.0),
+                 tr=0.8, phi=1.2, w=5.0, collision="MRT", shape=None, solid=None):
+    """D3Q19 single-component CS at T_r = 0.8 in a periodic sphere pack; liquid
+    slab x < nx/2, vapour elsewhere; uniform wetting phi."""
+    T, rv, rl, A = _cs(tr)
+    shape = shape or (n, n, n)
+    nz, ny, nx = shape
+    if solid is None:
+        solid = sphere_pack(shape, radii, porosity, seed)
+    rho = slab(shape, "x", 0, nx // 2, w, rl, rv)
+    wl = Workload("adjoint_pack", "D3Q19", tuple(shape), storage=storage, collision=collision,
+                  tau=(1.0, 1.0), eos_T=(T, T), A=(A, A), wet_mode=("PHI", "PHI"),
+                  wet=(phi, phi), rho_min=(rv, rv), rho_max=(rl, rl), steps=steps)
+    return wl, solid, rho[None]
+
+
+def single_phase_pack(n=128, seed=0, porosity=0.4, radii=(6.0, 14.0), accel=1e-5, storage="F32",
+                      steps=100, shape=None, solid=None):
+    """Single-phase flow (no interaction force) through a periodic sphere pack,
+    BGK tau = 1, rho = 1, driven by a body acceleration along x."""
+    shape = shape or (n, n, n)
+    if solid is None:
+        solid = sphere_pack(shape, radii, porosity, seed)
+    wl = Workload("single_phase_pack", "D3Q19", tuple(shape), storage=storage, collision="BGK",
+                  tau=(1.0, 1.0), psi_kind=("DENSITY", "DENSITY"), g=((0.0, 0.0), (0.0, 0.0)),
+                  A=(0.0, 0.0), body=(accel, 0.0, 0.0), rho_min=(0.0, 0.0), rho_max=(1e30, 1e30),
+                  steps=steps)
+    rho = np.ones((1,) + tuple(shape))
+    return wl, solid, rho

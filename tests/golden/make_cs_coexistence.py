@@ -1,0 +1,62 @@
+"""Write tests/golden/cs_coexistence.json from the oracle alone.
+
+For the Carnahan-Starling EOS with a = 1, b = 4, R = 1 (the paper's CS
+parameter set) this records, per reduced temperature T_r:
+  * T_c and the Maxwell equal-area coexistence densities (oracle/eos.py);
+  * the Zhang-Chen weight A of the force mix (Eq. 11/13) calibrated on a 1-D
+    flat liquid/vapour interface run with the FP64 oracle so that the steady
+    vapour density equals the Maxwell value.  The paper states only that A
+    (and alpha) were "adjusted for each EOS" to satisfy mechanical stability
+    (Sec. 3.1); this is that adjustment, with alpha = 1;
+  * the liquid and vapour densities the oracle reaches with that A.
+
+Run:  python tests/golden/make_cs_coexistence.py
+"""
+from __future__ import annotations
+
+import json
+import sys
+from pathlib import Path
+
+import numpy as np
+from scipy import optimize
+
+ROOT = Path(__file__).resolve().parents[2]
+sys.path.insert(0, str(ROOT))
+
+from oracle import eos, oracle  # noqa: E402
+from paper_2506_17713_amd import inputs  # noqa: E402
+
+OUT = Path(__file__).resolve().parent / "cs_coexistence.json"
+NX, STEPS = 200, 30000
+
+
+def flat_interface(T, rv, rl, A):
+    shape = (1, 1, NX)
+    w = inputs.Workload("flat", "D2Q9", shape, eos_T=(T, T), A=(A, A),
+                        rho_min=(rv, rv), rho_max=(rl, rl))
+    rho = inputs.slab(shape, "x", NX // 4, 3 * NX // 4, 5.0, rl, rv)
+    st = oracle.State(w, np.zeros(shape, np.uint8), rho[None])
+    st.step(STEPS)
+    r = st.fields()["rho"][0]
+    return float(r[NX // 2]), float(r[0])
+
+
+def main():
+    Tc, rc = eos.critical_point(eos.CS)
+    out = {"CS": {"a": 1.0, "b": 4.0, "R": 1.0, "alpha": 1.0, "Tc": Tc, "rho_c": rc,
+                  "lb_flat_interface": {"nx": NX, "steps": STEPS, "lattice": "D2Q9", "tau": 1.0}}}
+    for tr in (0.6, 0.7, 0.8, 0.9):
+        rv, rl, ps = eos.maxwell(eos.CS, tr)
+        T = tr * Tc
+        g = lambda A: flat_interface(T, rv, rl, A)[1] / rv - 1.0
+        A = optimize.brentq(g, -0.45, 0.0, xtol=1e-4)
+        lb_l, lb_v = flat_interface(T, rv, rl, A)
+        out["CS"][f"{tr:.1f}"] = {"T": T, "rho_v": rv, "rho_l": rl, "p_sat": ps, "A": A,
+                                  "lb_rho_v": lb_v, "lb_rho_l": lb_l}
+        print(tr, out["CS"][f"{tr:.1f}"], flush=True)
+    OUT.write_text(json.dumps(out, indent=1) + "\n")
+
+
+if __name__ == "__main__":
+    main()
