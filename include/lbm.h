@@ -1,0 +1,173 @@
+/*
+ * C-ABI of the MI355X multiphase lattice-Boltzmann library (liblbm.so).
+ *
+ * One handle advances one lattice on one HIP stream with a fused kernel per
+ * time step.  The step is the paper's Shan-Chen pseudopotential method for one
+ * or two fluid components (Sec. 2.1-2.4):
+ *   density and momentum moments                       (Eq. 4, Eq. 10)
+ *   improved virtual density at solid nodes             (Eq. 17)
+ *   EOS pseudopotential psi, U                          (Eq. 12)
+ *   Shan-Chen / Zhang-Chen interaction force            (Eq. 11, Eq. 13)
+ *   BGK or MRT collision with exact-difference forcing  (Eq. 3, Eq. 5)
+ *   streaming with halfway bounce-back                  (Eq. 1, Eq. 2)
+ * and observes densities and velocities with the half-force correction
+ * (Eq. 6).
+ *
+ * Conventions
+ *   - Every function returns LBM_OK (0) or a negative lbm_error code; no
+ *     exception or abort crosses the ABI.
+ *   - Arrays are in (z, y, x) order, x fastest.  A D2Q9 lattice has nz = 1
+ *     and its arrays are (y, x).
+ *   - "host" pointers are ordinary CPU memory, read during the call;
+ *     "device" pointers are HIP device memory owned by the caller.
+ *   - A handle is bound to the stream given to lbm_init; calls on one handle
+ *     are not thread-safe.  Work is enqueued asynchronously unless a function
+ *     says it synchronises.
+ *   - The compute type is double for LBM_STORE_F64 and float otherwise;
+ *     "compute-type" buffers below use it.
+ */
+#ifndef PAPER_2506_17713_LBM_H
+#define PAPER_2506_17713_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbm_error {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,         /* invalid argument or parameter combination   */
+    LBM_ERR_UNSUPPORTED = -2, /* valid but not provided by this build         */
+    LBM_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed   */
+    LBM_ERR_NONFINITE = -4,   /* a check found a non-finite or negative rho   */
+    LBM_ERR_SPACE = -5        /* workspace smaller than lbm_workspace_size   */
+} lbm_error;
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+enum { LBM_BGK = 0, LBM_MRT = 1 };
+/* Population storage.  F64 / F32 store f_i.  F16DEV / BF16DEV store the
+ * relative deviation h_i = f_i / (w_i rho*) - 1 in 16 bits plus the node's
+ * density rho* in FP32, and reconstruct f_i = w_i rho* (1 + h_i) in FP32. */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16DEV = 2, LBM_STORE_BF16DEV = 3 };
+/* Pseudopotential: Carnahan-Starling EOS (Eq. 12) or psi = rho. */
+enum { LBM_PSI_CS = 0, LBM_PSI_DENSITY = 1 };
+/* Improved virtual density (Eq. 17): rho_s = phi rho_ave or rho_ave - drho. */
+enum { LBM_WET_PHI = 0, LBM_WET_DRHO = 1 };
+
+#define LBM_MAX_COMP 2
+#define LBM_MAX_Q 19
+
+typedef struct lbm_params {
+    int32_t lattice;            /* LBM_D2Q9 or LBM_D3Q19                       */
+    int32_t nx, ny, nz;         /* lattice extent; nz = 1 for D2Q9             */
+    int32_t n_comp;             /* 1 or 2 fluid components                     */
+    int32_t collision;          /* LBM_BGK or LBM_MRT                          */
+    int32_t storage;            /* LBM_STORE_*                                 */
+    int32_t psi_kind[2];        /* LBM_PSI_* per component                     */
+    int32_t wet_mode[2];        /* LBM_WET_* per component                     */
+    int32_t common_velocity;    /* two components: 1 = common velocity u' =
+                                   sum_k(j^k/tau_k) / sum_k(rho^k/tau_k) in the
+                                   equilibria; 0 = each component's j^k/rho^k  */
+    int32_t check_every;        /* > 0: run the lbm_stats reduction every
+                                   check_every steps inside lbm_step and latch
+                                   LBM_ERR_NONFINITE; 0: checks on demand only  */
+    int32_t reserved[4];        /* must be zero                                */
+    double tau[2];              /* BGK relaxation time per component (> 0.5)   */
+    double mrt_s[2][19];        /* MRT relaxation rate of each moment row, rows
+                                   in the Lallemand-Luo (D2Q9) / d'Humieres
+                                   (D3Q19) order                               */
+    double eos_a[2], eos_b[2], eos_R[2];  /* Carnahan-Starling a, b, R         */
+    double eos_T[2];            /* absolute temperature                         */
+    double alpha[2];            /* EOS pressure scale alpha^k (Eq. 12)          */
+    double A[2];                /* Zhang-Chen weight A_kk (Eq. 13)              */
+    double g[2][2];             /* interaction strengths g_kk' (g_kk < 0 with
+                                   the EOS pseudopotential)                     */
+    double body_accel[3];       /* body acceleration (x, y, z): F^k += rho^k a  */
+    double wet[2];              /* uniform phi or drho when no per-node array   */
+    double rho_min[2], rho_max[2]; /* virtual-density limiter bounds            */
+} lbm_params;
+
+typedef struct lbm_stats_t {
+    int64_t step;               /* time steps taken since lbm_init              */
+    double mass[2];             /* sum of rho^k over fluid nodes                */
+    double momentum[3];         /* sum of the mixture momentum (Eq. 6)          */
+    double residual;            /* sum|u_x - u_x(prev)| / sum|u_x| against the
+                                   previous reduction (1.0 on the first one)    */
+    double saturation;          /* fraction of fluid nodes classified non-wetting:
+                                   rho^0 >= rho^1 (two components) or
+                                   rho < (rho_min + rho_max)/2 (one component)  */
+    double mean_ux;             /* mean mixture u_x over fluid nodes            */
+    int64_t n_fluid;            /* number of fluid nodes                        */
+    int32_t nonfinite;          /* count of fluid nodes with non-finite values  */
+    int32_t negative;           /* count of fluid nodes with rho^k < 0          */
+} lbm_stats_t;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Device bytes lbm_init needs in its workspace for these parameters: two
+ * population buffers (ping-pong), the per-node neighbour words, the wetting
+ * field, moment scratch and reduction partials.  Pure function.
+ * Errors: LBM_ERR_ARG for an invalid parameter set. */
+int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
+
+/* Create a handle and set the populations to the equilibrium of rho0/u0.
+ *   p          parameters, copied.
+ *   mask       host uint8[N], 1 = solid node (walls, grains), 0 = fluid.
+ *   rho0       host double[n_comp][N], initial density per component.
+ *   u0         host double[3][N] initial velocity (x, y, z), or NULL for rest.
+ *   wet        host double[n_comp][N] per-node phi / drho (used at solid
+ *              nodes), or NULL to use p->wet uniformly.
+ *   workspace  device buffer of ws_bytes >= lbm_workspace_size(p); owned by
+ *              the caller and must outlive the handle.
+ *   stream     hipStream_t on which all work of this handle is enqueued
+ *              (NULL = the null stream).
+ * Synchronises the stream before returning.
+ * Errors: LBM_ERR_ARG (bad parameters, NaN or negative rho0), LBM_ERR_SPACE,
+ * LBM_ERR_UNSUPPORTED, LBM_ERR_HIP. */
+int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const double* u0,
+             const double* wet, void* workspace, size_t ws_bytes, void* stream,
+             lbm_handle** out);
+
+/* Enqueue nsteps fused time steps (Eq. 1-17 in order) on the handle's stream.
+ * Asynchronous.  With check_every > 0 a reduction runs every check_every
+ * steps; a non-finite or negative density is reported by the next lbm_stats
+ * or lbm_sync.  Errors: LBM_ERR_ARG (nsteps < 0), LBM_ERR_HIP. */
+int lbm_step(lbm_handle* h, int64_t nsteps);
+
+/* Write the current density and velocity (Eq. 6, u = (j + F/2) / rho) into
+ * caller-owned device buffers of the compute type:
+ *   comp >= 0: rho_dev[N] = rho^comp, u_dev[3][N] = (j^comp + F^comp/2)/rho^comp
+ *   comp = -1: rho_dev[N] = sum_k rho^k, u_dev = sum_k(j^k + F^k/2)/sum_k rho^k
+ * Solid nodes get 0.  Either pointer may be NULL.  Asynchronous.
+ * Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
+int lbm_moments(lbm_handle* h, int comp, void* rho_dev, void* u_dev);
+
+/* Reduce the current state (FP64 accumulation, fixed order: bitwise
+ * reproducible) and copy the result to *out.  Synchronises the stream.
+ * Returns LBM_ERR_NONFINITE if this or a latched periodic check saw a
+ * non-finite or negative density (the latch is cleared). */
+int lbm_stats(lbm_handle* h, lbm_stats_t* out);
+
+/* Synchronise the stream; report a latched check failure or HIP error. */
+int lbm_sync(lbm_handle* h);
+
+/* Bytes of the raw population state (layout private to this library). */
+int lbm_state_bytes(const lbm_handle* h, size_t* bytes_out);
+/* Copy the raw state to / from a device buffer of lbm_state_bytes bytes
+ * (checkpoint and resume).  Asynchronous on the handle's stream. */
+int lbm_get_state(lbm_handle* h, void* dev_dst);
+int lbm_set_state(lbm_handle* h, const void* dev_src);
+
+/* Release the handle (not the caller's workspace).  NULL is ignored. */
+void lbm_free(lbm_handle* h);
+
+/* Static description of an error code. */
+const char* lbm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2506_17713_LBM_H */

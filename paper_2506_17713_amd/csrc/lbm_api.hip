@@ -1,0 +1,597 @@
+// C-ABI of liblbm.so: handle management, workspace carving, kernel dispatch
+// and the FP64 reductions behind lbm_stats.  Declarations: include/lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kRedBlocks = 1024;  // partial sums of the first reduction pass
+constexpr int kRedThreads = 256;
+constexpr int kStatSlots = 16;    // doubles per partial / in the result
+
+struct Layout {
+    size_t fA, fB, rA, rB, nbr, wet, mrho, mu, uxprev, partial, dstats, total;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int q_of(int lat) { return lat == LBM_D2Q9 ? 9 : 19; }
+size_t store_bytes(int st) { return st == LBM_STORE_F64 ? 8 : (st == LBM_STORE_F32 ? 4 : 2); }
+size_t real_bytes(int st) { return st == LBM_STORE_F64 ? 8 : 4; }
+bool is_dev(int st) { return st == LBM_STORE_F16DEV || st == LBM_STORE_BF16DEV; }
+
+int validate(const lbm_params* p) {
+    if (!p) return LBM_ERR_ARG;
+    if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19) return LBM_ERR_ARG;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LBM_ERR_ARG;
+    if (p->lattice == LBM_D2Q9 && p->nz != 1) return LBM_ERR_ARG;
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    if (N >= (1LL << 31)) return LBM_ERR_ARG;
+    if (p->n_comp < 1 || p->n_comp > 2) return LBM_ERR_ARG;
+    if (p->collision != LBM_BGK && p->collision != LBM_MRT) return LBM_ERR_ARG;
+    if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_BF16DEV) return LBM_ERR_ARG;
+    if (p->check_every < 0) return LBM_ERR_ARG;
+    for (int i = 0; i < 4; ++i)
+        if (p->reserved[i] != 0) return LBM_ERR_ARG;
+    for (int k = 0; k < p->n_comp; ++k) {
+        if (!(p->tau[k] > 0.5) || !std::isfinite(p->tau[k])) return LBM_ERR_ARG;
+        if (p->psi_kind[k] != LBM_PSI_CS && p->psi_kind[k] != LBM_PSI_DENSITY) return LBM_ERR_ARG;
+        if (p->wet_mode[k] != LBM_WET_PHI && p->wet_mode[k] != LBM_WET_DRHO) return LBM_ERR_ARG;
+        if (!(p->rho_min[k] <= p->rho_max[k])) return LBM_ERR_ARG;
+        if (p->collision == LBM_MRT)
+            for (int m = 0; m < q_of(p->lattice); ++m)
+                if (!(p->mrt_s[k][m] >= 0.0 && p->mrt_s[k][m] < 2.0)) return LBM_ERR_ARG;
+        if (p->psi_kind[k] == LBM_PSI_CS) {
+            // Eq. 12 needs g_kk < 0; the square-root argument must stay
+            // non-negative over the densities the limiter admits
+            if (!(p->g[k][k] < 0.0)) return LBM_ERR_ARG;
+            if (!(p->eos_b[k] > 0.0) || !(p->eos_T[k] > 0.0)) return LBM_ERR_ARG;
+            const double hi = p->rho_max[k];
+            if (hi < 1e10) {
+                for (int s = 0; s <= 64; ++s) {
+                    const double r = p->rho_min[k] + (hi - p->rho_min[k]) * s / 64.0;
+                    const double eta = p->eos_b[k] * r / 4.0;
+                    if (eta >= 1.0) return LBM_ERR_ARG;
+                    const double pe = r * p->eos_R[k] * p->eos_T[k] * (1 + eta + eta * eta - eta * eta * eta) /
+                                          ((1 - eta) * (1 - eta) * (1 - eta)) -
+                                      p->eos_a[k] * r * r;
+                    if (p->alpha[k] * pe - r / 3.0 > 1e-12) return LBM_ERR_ARG;
+                }
+            }
+        }
+    }
+    return LBM_OK;
+}
+
+Layout layout_of(const lbm_params* p) {
+    Layout L{};
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    const size_t nc = p->n_comp, q = q_of(p->lattice);
+    const size_t sb = store_bytes(p->storage), rb = real_bytes(p->storage);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    // lbm_init stages the mask, rho0 and u0 in the second buffer
+    const size_t stage = align256(N) + align256(nc * N * rb) + align256(3 * N * rb);
+    const size_t pop = nc * q * N * sb;
+    L.fA = take(pop);
+    L.fB = take(pop > stage ? pop : stage);
+    L.rA = take(is_dev(p->storage) ? nc * N * 4 : 0);
+    L.rB = take(is_dev(p->storage) ? nc * N * 4 : 0);
+    L.nbr = take(N * 4);
+    L.wet = take(nc * N * rb);
+    L.mrho = take(nc * N * rb);
+    L.mu = take(3 * N * rb);
+    L.uxprev = take(N * rb);
+    L.partial = take((size_t)kRedBlocks * kStatSlots * 8);
+    L.dstats = take(kStatSlots * 8 + 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_handle {
+    lbm_params p;
+    Layout lay;
+    hipStream_t stream;
+    char* ws;
+    int N, NA, NB, NCc;
+    int cur;          // 0: state in fA/rA, 1: state in fB/rB
+    int64_t step;
+    int64_t since_check;
+    bool have_prev;
+    int chunk_override;
+};
+
+namespace {
+
+template <class R>
+void fill_args(lbm_handle* h, StepArgs<R>& a) {
+    const lbm_params& p = h->p;
+    std::memset(&a, 0, sizeof(a));
+    char* ws = h->ws;
+    const bool dev = is_dev(p.storage);
+    a.fin = ws + (h->cur ? h->lay.fB : h->lay.fA);
+    a.fout = ws + (h->cur ? h->lay.fA : h->lay.fB);
+    a.rin = dev ? reinterpret_cast<const float*>(ws + (h->cur ? h->lay.rB : h->lay.rA)) : nullptr;
+    a.rout = dev ? reinterpret_cast<float*>(ws + (h->cur ? h->lay.rA : h->lay.rB)) : nullptr;
+    a.nbr = reinterpret_cast<const uint32_t*>(ws + h->lay.nbr);
+    a.wet = reinterpret_cast<const R*>(ws + h->lay.wet);
+    a.NA = h->NA;
+    a.NB = h->NB;
+    a.NC_ = h->NCc;
+    a.N = h->N;
+    a.common_u = p.common_velocity ? 1 : 0;
+    a.has_zc = 0;
+    const int q = q_of(p.lattice);
+    for (int k = 0; k < p.n_comp; ++k) {
+        a.psi_cs[k] = p.psi_kind[k] == LBM_PSI_CS;
+        a.wet_drho[k] = p.wet_mode[k] == LBM_WET_DRHO;
+        a.omega[k] = (R)(1.0 / p.tau[k]);
+        for (int m = 0; m < q; ++m) {
+            const double nrm = p.lattice == LBM_D2Q9 ? mrt_norm<LAT_D2Q9>(m) : mrt_norm<LAT_D3Q19>(m);
+            a.srate[k][m] = (R)(p.mrt_s[k][m] / nrm);
+        }
+        a.eos_a[k] = (R)p.eos_a[k];
+        a.eos_b[k] = (R)p.eos_b[k];
+        a.eos_RT[k] = (R)(p.eos_R[k] * p.eos_T[k]);
+        a.alpha[k] = (R)p.alpha[k];
+        a.ginv[k] = p.g[k][k] != 0.0 ? (R)(1.0 / p.g[k][k]) : (R)0;
+        a.A[k] = (R)p.A[k];
+        if (p.A[k] != 0.0 && p.psi_kind[k] == LBM_PSI_CS) a.has_zc = 1;
+        for (int kk = 0; kk < p.n_comp; ++kk) a.g[k][kk] = (R)p.g[k][kk];
+        a.rho_min[k] = (R)p.rho_min[k];
+        a.rho_max[k] = (R)p.rho_max[k];
+    }
+    for (int d = 0; d < 3; ++d) a.body[d] = (R)p.body_accel[d];
+}
+
+template <int LAT, int NC, int ST, int COLL, bool MOM>
+hipError_t launch_step(lbm_handle* h, StepArgs<typename Store<ST>::R>& a) {
+    constexpr int TA = LAT == LAT_D2Q9 ? 64 : 32;
+    constexpr int TB = LAT == LAT_D2Q9 ? 1 : (ST == ST_F64 ? 4 : 8);
+    a.tiles_a = (h->NA + TA - 1) / TA;
+    a.tiles_b = (h->NB + TB - 1) / TB;
+    const int tiles = a.tiles_a * a.tiles_b;
+    int chunk = h->chunk_override;
+    if (chunk <= 0) {
+        const int want = (2048 + tiles - 1) / tiles;  // chunks for about 2048 workgroups
+        chunk = (h->NCc + want - 1) / want;
+        const int minc = LAT == LAT_D2Q9 ? 4 : 8;
+        if (chunk < minc) chunk = minc;
+    }
+    if (chunk > h->NCc) chunk = h->NCc;
+    a.chunk = chunk;
+    const int nchunks = (h->NCc + chunk - 1) / chunk;
+    const int nblk = tiles * nchunks;
+    hipLaunchKernelGGL((k_step<LAT, NC, ST, COLL, MOM, TA, TB>), dim3(nblk), dim3(TA * TB), 0,
+                       h->stream, a);
+    return hipGetLastError();
+}
+
+template <int LAT, int NC, int ST>
+hipError_t dispatch_coll(lbm_handle* h, bool mom, StepArgs<typename Store<ST>::R>& a) {
+    if (mom) return launch_step<LAT, NC, ST, COLL_BGK, true>(h, a);
+    if (h->p.collision == LBM_MRT) return launch_step<LAT, NC, ST, COLL_MRT, false>(h, a);
+    return launch_step<LAT, NC, ST, COLL_BGK, false>(h, a);
+}
+
+template <int LAT, int NC>
+hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u) {
+    switch (h->p.storage) {
+        case LBM_STORE_F64: {
+            StepArgs<double> a;
+            fill_args(h, a);
+            a.mom_comp = comp;
+            a.mom_rho = (double*)rho;
+            a.mom_u = (double*)u;
+            return dispatch_coll<LAT, NC, ST_F64>(h, mom, a);
+        }
+        case LBM_STORE_F32: {
+            StepArgs<float> a;
+            fill_args(h, a);
+            a.mom_comp = comp;
+            a.mom_rho = (float*)rho;
+            a.mom_u = (float*)u;
+            return dispatch_coll<LAT, NC, ST_F32>(h, mom, a);
+        }
+        case LBM_STORE_F16DEV: {
+            StepArgs<float> a;
+            fill_args(h, a);
+            a.mom_comp = comp;
+            a.mom_rho = (float*)rho;
+            a.mom_u = (float*)u;
+            return dispatch_coll<LAT, NC, ST_F16>(h, mom, a);
+        }
+        default: {
+            StepArgs<float> a;
+            fill_args(h, a);
+            a.mom_comp = comp;
+            a.mom_rho = (float*)rho;
+            a.mom_u = (float*)u;
+            return dispatch_coll<LAT, NC, ST_BF16>(h, mom, a);
+        }
+    }
+}
+
+hipError_t run_kernel(lbm_handle* h, bool mom, int comp = -1, void* rho = nullptr, void* u = nullptr) {
+    const bool d2 = h->p.lattice == LBM_D2Q9;
+    if (d2) {
+        if (h->p.n_comp == 1) return dispatch_store<LAT_D2Q9, 1>(h, mom, comp, rho, u);
+        return dispatch_store<LAT_D2Q9, 2>(h, mom, comp, rho, u);
+    }
+    if (h->p.n_comp == 1) return dispatch_store<LAT_D3Q19, 1>(h, mom, comp, rho, u);
+    return dispatch_store<LAT_D3Q19, 2>(h, mom, comp, rho, u);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (FP64 accumulators, wavefront shuffles, fixed order).
+// Slots: 0,1 mass; 2,3,4 momentum; 5 sum|ux-prev|; 6 sum|ux|; 7 sum ux;
+//        8 non-wetting count; 9 fluid count; 10 non-finite; 11 negative.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kRedThreads)
+    k_reduce1(const R* __restrict__ rho, const R* __restrict__ u, R* __restrict__ uxprev,
+              const uint32_t* __restrict__ nbr, double* __restrict__ partial, int N, int nc,
+              int have_prev, R rho_mid) {
+    double acc[12];
+#pragma unroll
+    for (int s = 0; s < 12; ++s) acc[s] = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
+        if (nbr[n] & 1u) continue;
+        const double r0 = rho[n];
+        const double r1 = nc > 1 ? (double)rho[(size_t)N + n] : 0.0;
+        const double rt = r0 + r1;
+        const double ux = u[n], uy = u[(size_t)N + n], uz = u[2 * (size_t)N + n];
+        const double prev = have_prev ? (double)uxprev[n] : 0.0;
+        uxprev[n] = (R)ux;
+        acc[0] += r0;
+        acc[1] += r1;
+        acc[2] += rt * ux;
+        acc[3] += rt * uy;
+        acc[4] += rt * uz;
+        acc[5] += fabs(ux - prev);
+        acc[6] += fabs(ux);
+        acc[7] += ux;
+        acc[8] += nc > 1 ? (r0 >= r1 ? 1.0 : 0.0) : (r0 < (double)rho_mid ? 1.0 : 0.0);
+        acc[9] += 1.0;
+        const bool fin = std::isfinite(r0) && std::isfinite(r1) && std::isfinite(ux) && std::isfinite(uy) &&
+                         std::isfinite(uz);
+        acc[10] += fin ? 0.0 : 1.0;
+        acc[11] += (r0 < 0.0 || r1 < 0.0) ? 1.0 : 0.0;
+    }
+    __shared__ double sh[kRedThreads / 64][12];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < 12; ++s) {
+        const double v = wave_sum(acc[s]);
+        if (lane == 0) sh[wv][s] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        double v = 0.0;
+        for (int w = 0; w < kRedThreads / 64; ++w) v += sh[w][threadIdx.x];
+        partial[(size_t)blockIdx.x * kStatSlots + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_reduce2(const double* __restrict__ partial, double* __restrict__ out, int nblk) {
+    // one wavefront per slot, fixed order
+    const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (s >= 12) return;
+    double v = 0.0;
+    for (int b = lane; b < nblk; b += 64) v += partial[(size_t)b * kStatSlots + s];
+    v = wave_sum(v);
+    if (lane == 0) {
+        out[s] = v;
+        if (s == 10 || s == 11) {
+            // sticky failure flag after the result slots
+            if (v > 0.0) reinterpret_cast<unsigned long long*>(out + kStatSlots)[0] = 1ull;
+        }
+    }
+}
+
+hipError_t enqueue_stats(lbm_handle* h) {
+    char* ws = h->ws;
+    const size_t rb = real_bytes(h->p.storage);
+    hipError_t e;
+    for (int k = 0; k < h->p.n_comp; ++k) {
+        e = run_kernel(h, true, k, ws + h->lay.mrho + (size_t)k * h->N * rb, nullptr);
+        if (e != hipSuccess) return e;
+    }
+    e = run_kernel(h, true, -1, nullptr, ws + h->lay.mu);
+    if (e != hipSuccess) return e;
+    const double mid = 0.5 * (h->p.rho_min[0] + h->p.rho_max[0]);
+    const uint32_t* nbr = reinterpret_cast<const uint32_t*>(ws + h->lay.nbr);
+    double* part = reinterpret_cast<double*>(ws + h->lay.partial);
+    if (h->p.storage == LBM_STORE_F64) {
+        hipLaunchKernelGGL(k_reduce1<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream,
+                           reinterpret_cast<const double*>(ws + h->lay.mrho),
+                           reinterpret_cast<const double*>(ws + h->lay.mu),
+                           reinterpret_cast<double*>(ws + h->lay.uxprev), nbr, part, h->N, h->p.n_comp,
+                           h->have_prev ? 1 : 0, mid);
+    } else {
+        hipLaunchKernelGGL(k_reduce1<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream,
+                           reinterpret_cast<const float*>(ws + h->lay.mrho),
+                           reinterpret_cast<const float*>(ws + h->lay.mu),
+                           reinterpret_cast<float*>(ws + h->lay.uxprev), nbr, part, h->N, h->p.n_comp,
+                           h->have_prev ? 1 : 0, (float)mid);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(12 * 64), 0, h->stream, part,
+                       reinterpret_cast<double*>(ws + h->lay.dstats), kRedBlocks);
+    h->have_prev = true;
+    return hipGetLastError();
+}
+
+template <class R>
+std::vector<R> to_real(const double* src, size_t n) {
+    std::vector<R> v(n);
+    for (size_t i = 0; i < n; ++i) v[i] = (R)src[i];
+    return v;
+}
+
+template <int LAT, int NC, int ST>
+hipError_t launch_init(lbm_handle* h, const void* rho0, const void* u0) {
+    const int N = h->N;
+    const int blk = 256, grid = (N + blk - 1) / blk;
+    using R = typename Store<ST>::R;
+    hipLaunchKernelGGL((k_init<LAT, NC, ST>), dim3(grid), dim3(blk), 0, h->stream, (const R*)rho0,
+                       (const R*)u0, reinterpret_cast<const uint32_t*>(h->ws + h->lay.nbr), h->ws + h->lay.fA,
+                       is_dev(h->p.storage) ? reinterpret_cast<float*>(h->ws + h->lay.rA) : nullptr, h->NA,
+                       h->NB, h->NCc);
+    return hipGetLastError();
+}
+
+template <int LAT, int NC>
+hipError_t init_store(lbm_handle* h, const void* rho0, const void* u0) {
+    switch (h->p.storage) {
+        case LBM_STORE_F64: return launch_init<LAT, NC, ST_F64>(h, rho0, u0);
+        case LBM_STORE_F32: return launch_init<LAT, NC, ST_F32>(h, rho0, u0);
+        case LBM_STORE_F16DEV: return launch_init<LAT, NC, ST_F16>(h, rho0, u0);
+        default: return launch_init<LAT, NC, ST_BF16>(h, rho0, u0);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_strerror(int code) {
+    switch (code) {
+        case LBM_OK: return "ok";
+        case LBM_ERR_ARG: return "invalid argument";
+        case LBM_ERR_UNSUPPORTED: return "unsupported configuration";
+        case LBM_ERR_HIP: return "HIP runtime error";
+        case LBM_ERR_NONFINITE: return "non-finite or negative density detected";
+        case LBM_ERR_SPACE: return "workspace too small";
+        default: return "unknown error";
+    }
+}
+
+int lbm_workspace_size(const lbm_params* p, size_t* bytes_out) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!bytes_out) return LBM_ERR_ARG;
+    *bytes_out = layout_of(p).total;
+    return LBM_OK;
+}
+
+int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const double* u0,
+             const double* wet, void* workspace, size_t ws_bytes, void* stream, lbm_handle** out) {
+    if (!out || !mask || !rho0 || !workspace) return LBM_ERR_ARG;
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    Layout lay = layout_of(p);
+    if (ws_bytes < lay.total) return LBM_ERR_SPACE;
+    if (((uintptr_t)workspace & 255u) != 0) return LBM_ERR_ARG;
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    const int nc = p->n_comp;
+    for (size_t n = 0; n < N; ++n) {
+        if (mask[n]) continue;
+        for (int k = 0; k < nc; ++k) {
+            const double r = rho0[k * N + n];
+            if (!std::isfinite(r) || r <= 0.0) return LBM_ERR_ARG;
+        }
+        if (u0)
+            for (int d = 0; d < 3; ++d)
+                if (!std::isfinite(u0[d * N + n])) return LBM_ERR_ARG;
+    }
+    lbm_handle* h = new (std::nothrow) lbm_handle();
+    if (!h) return LBM_ERR_ARG;
+    h->p = *p;
+    h->lay = lay;
+    h->stream = (hipStream_t)stream;
+    h->ws = (char*)workspace;
+    h->N = (int)N;
+    h->NA = p->nx;
+    h->NB = p->lattice == LBM_D2Q9 ? 1 : p->ny;
+    h->NCc = p->lattice == LBM_D2Q9 ? p->ny : p->nz;
+    h->cur = 0;
+    h->step = 0;
+    h->since_check = 0;
+    h->have_prev = false;
+    const char* ch = std::getenv("LBM_CHUNK");
+    h->chunk_override = ch ? std::atoi(ch) : 0;
+
+    const size_t rb = real_bytes(p->storage);
+    // stage mask, rho0 and u0 in the second population buffer
+    char* stage = h->ws + lay.fB;
+    char* d_mask = stage;
+    char* d_rho = stage + align256(N);
+    char* d_u = d_rho + align256(nc * N * rb);
+    hipError_t e = hipSuccess;
+    std::vector<double> hd;
+    std::vector<float> hf;
+    auto upload = [&](void* dst, const double* src, size_t n) -> hipError_t {
+        if (rb == 8) return hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, h->stream);
+        hf = to_real<float>(src, n);
+        hipError_t r = hipMemcpyAsync(dst, hf.data(), n * 4, hipMemcpyHostToDevice, h->stream);
+        if (r == hipSuccess) r = hipStreamSynchronize(h->stream);
+        return r;
+    };
+    e = hipMemcpyAsync(d_mask, mask, N, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = upload(d_rho, rho0, nc * N);
+    if (e == hipSuccess && u0) e = upload(d_u, u0, 3 * N);
+    // wetting field
+    if (e == hipSuccess) {
+        if (wet) {
+            e = upload(h->ws + lay.wet, wet, nc * N);
+        } else {
+            std::vector<double> uni(nc * N);
+            for (int k = 0; k < nc; ++k)
+                for (size_t n = 0; n < N; ++n) uni[k * N + n] = p->wet[k];
+            e = upload(h->ws + lay.wet, uni.data(), nc * N);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        }
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + lay.dstats, 0, kStatSlots * 8 + 8, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + lay.fA, 0, lay.fB - lay.fA, h->stream);
+    if (e == hipSuccess) {
+        const int blk = 256, grid = (int)((N + blk - 1) / blk);
+        if (p->lattice == LBM_D2Q9)
+            hipLaunchKernelGGL(k_nbr_words<LAT_D2Q9>, dim3(grid), dim3(blk), 0, h->stream,
+                               (const uint8_t*)d_mask, (uint32_t*)(h->ws + lay.nbr), h->NA, h->NB, h->NCc);
+        else
+            hipLaunchKernelGGL(k_nbr_words<LAT_D3Q19>, dim3(grid), dim3(blk), 0, h->stream,
+                               (const uint8_t*)d_mask, (uint32_t*)(h->ws + lay.nbr), h->NA, h->NB, h->NCc);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        const void* du = u0 ? d_u : nullptr;
+        if (p->lattice == LBM_D2Q9)
+            e = nc == 1 ? init_store<LAT_D2Q9, 1>(h, d_rho, du) : init_store<LAT_D2Q9, 2>(h, d_rho, du);
+        else
+            e = nc == 1 ? init_store<LAT_D3Q19, 1>(h, d_rho, du) : init_store<LAT_D3Q19, 2>(h, d_rho, du);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + lay.fB, 0, lay.rA - lay.fB, h->stream);
+    if (e == hipSuccess && lay.nbr > lay.rB) e = hipMemsetAsync(h->ws + lay.rB, 0, lay.nbr - lay.rB, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return LBM_ERR_HIP;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int64_t nsteps) {
+    if (!h || nsteps < 0) return LBM_ERR_ARG;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (run_kernel(h, false) != hipSuccess) return LBM_ERR_HIP;
+        h->cur ^= 1;
+        h->step += 1;
+        if (h->p.check_every > 0 && ++h->since_check >= h->p.check_every) {
+            h->since_check = 0;
+            if (enqueue_stats(h) != hipSuccess) return LBM_ERR_HIP;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_handle* h, int comp, void* rho_dev, void* u_dev) {
+    if (!h || comp < -1 || comp >= h->p.n_comp) return LBM_ERR_ARG;
+    if (!rho_dev && !u_dev) return LBM_OK;
+    return run_kernel(h, true, comp, rho_dev, u_dev) == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+static int read_flag(lbm_handle* h, double* res) {
+    double buf[kStatSlots + 1];
+    if (hipMemcpyAsync(buf, h->ws + h->lay.dstats, sizeof(buf), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+        return LBM_ERR_HIP;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LBM_ERR_HIP;
+    if (res) std::memcpy(res, buf, sizeof(double) * kStatSlots);
+    unsigned long long flag;
+    std::memcpy(&flag, &buf[kStatSlots], 8);
+    if (flag) {
+        hipMemsetAsync(h->ws + h->lay.dstats + kStatSlots * 8, 0, 8, h->stream);
+        hipStreamSynchronize(h->stream);
+        return LBM_ERR_NONFINITE;
+    }
+    return LBM_OK;
+}
+
+int lbm_stats(lbm_handle* h, lbm_stats_t* out) {
+    if (!h || !out) return LBM_ERR_ARG;
+    if (enqueue_stats(h) != hipSuccess) return LBM_ERR_HIP;
+    double r[kStatSlots];
+    const int rc = read_flag(h, r);
+    if (rc == LBM_ERR_HIP) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->step = h->step;
+    out->mass[0] = r[0];
+    out->mass[1] = r[1];
+    out->momentum[0] = r[2];
+    out->momentum[1] = r[3];
+    out->momentum[2] = r[4];
+    out->residual = r[6] > 0.0 ? r[5] / r[6] : 0.0;
+    out->saturation = r[9] > 0.0 ? r[8] / r[9] : 0.0;
+    out->mean_ux = r[9] > 0.0 ? r[7] / r[9] : 0.0;
+    out->n_fluid = (int64_t)r[9];
+    out->nonfinite = (int32_t)r[10];
+    out->negative = (int32_t)r[11];
+    return rc;
+}
+
+int lbm_sync(lbm_handle* h) {
+    if (!h) return LBM_ERR_ARG;
+    return read_flag(h, nullptr);
+}
+
+int lbm_state_bytes(const lbm_handle* h, size_t* bytes_out) {
+    if (!h || !bytes_out) return LBM_ERR_ARG;
+    const size_t N = h->N;
+    *bytes_out = (size_t)h->p.n_comp * q_of(h->p.lattice) * N * store_bytes(h->p.storage) +
+                 (is_dev(h->p.storage) ? (size_t)h->p.n_comp * N * 4 : 0);
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_handle* h, void* dev_dst) {
+    if (!h || !dev_dst) return LBM_ERR_ARG;
+    const size_t N = h->N;
+    const size_t fb = (size_t)h->p.n_comp * q_of(h->p.lattice) * N * store_bytes(h->p.storage);
+    hipError_t e = hipMemcpyAsync(dev_dst, h->ws + (h->cur ? h->lay.fB : h->lay.fA), fb,
+                                  hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess && is_dev(h->p.storage))
+        e = hipMemcpyAsync((char*)dev_dst + fb, h->ws + (h->cur ? h->lay.rB : h->lay.rA),
+                           (size_t)h->p.n_comp * N * 4, hipMemcpyDeviceToDevice, h->stream);
+    return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+int lbm_set_state(lbm_handle* h, const void* dev_src) {
+    if (!h || !dev_src) return LBM_ERR_ARG;
+    const size_t N = h->N;
+    const size_t fb = (size_t)h->p.n_comp * q_of(h->p.lattice) * N * store_bytes(h->p.storage);
+    hipError_t e = hipMemcpyAsync(h->ws + (h->cur ? h->lay.fB : h->lay.fA), dev_src, fb,
+                                  hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess && is_dev(h->p.storage))
+        e = hipMemcpyAsync(h->ws + (h->cur ? h->lay.rB : h->lay.rA), (const char*)dev_src + fb,
+                           (size_t)h->p.n_comp * N * 4, hipMemcpyDeviceToDevice, h->stream);
+    return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+void lbm_free(lbm_handle* h) { delete h; }
+
+}  // extern "C"
