@@ -160,6 +160,57 @@ int lbm_state_bytes(const lbm_handle* h, size_t* bytes_out);
 int lbm_get_state(lbm_handle* h, void* dev_dst);
 int lbm_set_state(lbm_handle* h, const void* dev_src);
 
+/* ------------------------------------------------------------------------
+ * Gradients by the hand-written adjoint of the fused step (reverse mode).
+ * The paper differentiates its solver end to end with JAX (Sec. 4); this is
+ * the same derivative, computed by an explicit adjoint of every step (Eq. 1-17
+ * in reverse) with checkpointing every ckpt_every steps.
+ *
+ * Observables of the density rho(x) at the final step:
+ *   LBM_OBS_SATURATION  L = (1/N_fluid) sum_fluid sigma((rho_mid - rho) / delta),
+ *                       a smooth fraction of fluid nodes below rho_mid (the
+ *                       non-wetting vapour); sigma is the logistic function.
+ *                       (Sec. 3.4.3 segments by threshold; the step function
+ *                       has no derivative, the logistic one does.)
+ *   LBM_OBS_DRHO        L = sum_x dL_drho[x] rho(x) with a caller-given device
+ *                       array dL_drho[N] of the compute type (any objective
+ *                       linearised in the final density).
+ * Supported for one component with LBM_STORE_F32 or LBM_STORE_F64; other
+ * configurations return LBM_ERR_UNSUPPORTED.
+ * ------------------------------------------------------------------------ */
+enum { LBM_OBS_SATURATION = 0, LBM_OBS_DRHO = 1 };
+
+typedef struct lbm_grad_req {
+    int32_t observable;         /* LBM_OBS_*                                    */
+    int32_t nsteps;             /* forward horizon (>= 1)                       */
+    int32_t ckpt_every;         /* checkpoint interval K (>= 1)                 */
+    int32_t reserved;           /* must be zero                                 */
+    double rho_mid, delta;      /* LBM_OBS_SATURATION parameters (delta > 0)    */
+    const void* dL_drho;        /* LBM_OBS_DRHO: device array [N]               */
+    void* ws;                   /* device workspace, 256-byte aligned, owned by
+                                   the caller: checkpoints, one segment of states
+                                   and the adjoint fields                       */
+    size_t ws_bytes;
+} lbm_grad_req;
+
+/* Device bytes lbm_grad needs in r->ws for this handle and request:
+ * ceil(nsteps/K) checkpoints plus K recomputed states (each q*N values of the
+ * compute type) and about 2q + 15 values per node of adjoint fields.
+ * Errors: LBM_ERR_ARG, LBM_ERR_UNSUPPORTED. */
+int lbm_grad_workspace_size(const lbm_handle* h, const lbm_grad_req* r, size_t* bytes_out);
+
+/* Starting from the handle's current state, run nsteps forward steps (the
+ * handle ends advanced by nsteps, as after lbm_step), evaluate L and
+ * back-propagate.  Outputs:
+ *   L_out      host: value of the observable (may be NULL)
+ *   dwet_dev   device double[N]: dL / d(wetting parameter) per node (phi or
+ *              drho by wet_mode), non-zero only at solid nodes next to fluid
+ *              whose virtual density is not at a limiter bound
+ *   dT_out     host: dL / d eos_T[0] (absolute temperature; may be NULL)
+ * Synchronises the stream.  Errors: LBM_ERR_ARG, LBM_ERR_SPACE,
+ * LBM_ERR_UNSUPPORTED, LBM_ERR_HIP. */
+int lbm_grad(lbm_handle* h, const lbm_grad_req* r, double* L_out, double* dwet_dev, double* dT_out);
+
 /* Release the handle (not the caller's workspace).  NULL is ignored. */
 void lbm_free(lbm_handle* h);
 

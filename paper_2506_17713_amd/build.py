@@ -9,7 +9,7 @@ HERE = Path(__file__).resolve().parent
 ROOT = HERE.parent
 CSRC = HERE / "csrc"
 OUT = HERE / "_lib" / "liblbm.so"
-SOURCES = ["lbm_api.hip"]
+SOURCES = ["lbm_api.hip", "lbm_adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -21,15 +21,30 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> Path:
+    """Compile every translation unit (in parallel) and link liblbm.so."""
     OUT.parent.mkdir(exist_ok=True)
+    objdir = HERE / "_build"
+    objdir.mkdir(exist_ok=True)
+    inc = [f"-I{ROOT / 'include'}", f"-I{CSRC}"]
+    procs = []
+    for s in SOURCES:
+        obj = objdir / (Path(s).stem + ".o")
+        cmd = [HIPCC, *FLAGS, "-c", *inc, str(CSRC / s), "-o", str(obj)]
+        cmd.remove("-shared")
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    objs = []
+    for cmd, obj, p in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"hipcc failed: {' '.join(cmd)}\n{out}\n{err}")
+        objs.append(str(obj))
     tmp = OUT.with_suffix(".so.tmp")
-    cmd = [HIPCC, *FLAGS, f"-I{ROOT / 'include'}", f"-I{CSRC}", *[str(CSRC / s) for s in SOURCES],
-           "-o", str(tmp)]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", str(tmp)]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed:\n{res.stdout}\n{res.stderr}")
+        raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, OUT)
     return OUT
 

@@ -8,27 +8,23 @@
 #include <new>
 #include <vector>
 
-#include "lbm.h"
-#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
 
 using namespace lbm;
+using namespace lbmi;
+
+// Build-time tile configuration of the 3-D 32-bit kernels: tile height along y
+// (the tile is 32 x LBM_TILE_B nodes) and whether own-node populations are
+// carried in registers from the pull to the collision.
+#ifndef LBM_TILE_B
+#define LBM_TILE_B 8
+#endif
+#ifndef LBM_CARRY
+#define LBM_CARRY 1
+#endif
 
 namespace {
 
-constexpr int kRedBlocks = 1024;  // partial sums of the first reduction pass
-constexpr int kRedThreads = 256;
-constexpr int kStatSlots = 16;    // doubles per partial / in the result
-
-struct Layout {
-    size_t fA, fB, rA, rB, nbr, wet, mrho, mu, uxprev, partial, dstats, total;
-};
-
-inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-int q_of(int lat) { return lat == LBM_D2Q9 ? 9 : 19; }
-size_t store_bytes(int st) { return st == LBM_STORE_F64 ? 8 : (st == LBM_STORE_F32 ? 4 : 2); }
-size_t real_bytes(int st) { return st == LBM_STORE_F64 ? 8 : 4; }
-bool is_dev(int st) { return st == LBM_STORE_F16DEV || st == LBM_STORE_BF16DEV; }
 
 int validate(const lbm_params* p) {
     if (!p) return LBM_ERR_ARG;
@@ -104,23 +100,10 @@ Layout layout_of(const lbm_params* p) {
 
 }  // namespace
 
-struct lbm_handle {
-    lbm_params p;
-    Layout lay;
-    hipStream_t stream;
-    char* ws;
-    int N, NA, NB, NCc;
-    int cur;          // 0: state in fA/rA, 1: state in fB/rB
-    int64_t step;
-    int64_t since_check;
-    bool have_prev;
-    int chunk_override;
-};
-
 namespace {
 
 template <class R>
-void fill_args(lbm_handle* h, StepArgs<R>& a) {
+void fill_args(lbm_handle* h, StepArgs<R>& a, const Buffers* bufs) {
     const lbm_params& p = h->p;
     std::memset(&a, 0, sizeof(a));
     char* ws = h->ws;
@@ -129,6 +112,12 @@ void fill_args(lbm_handle* h, StepArgs<R>& a) {
     a.fout = ws + (h->cur ? h->lay.fA : h->lay.fB);
     a.rin = dev ? reinterpret_cast<const float*>(ws + (h->cur ? h->lay.rB : h->lay.rA)) : nullptr;
     a.rout = dev ? reinterpret_cast<float*>(ws + (h->cur ? h->lay.rA : h->lay.rB)) : nullptr;
+    if (bufs) {
+        a.fin = bufs->fin;
+        a.fout = bufs->fout;
+        a.rin = bufs->rin;
+        a.rout = bufs->rout;
+    }
     a.nbr = reinterpret_cast<const uint32_t*>(ws + h->lay.nbr);
     a.wet = reinterpret_cast<const R*>(ws + h->lay.wet);
     a.NA = h->NA;
@@ -163,7 +152,7 @@ void fill_args(lbm_handle* h, StepArgs<R>& a) {
 template <int LAT, int NC, int ST, int COLL, bool MOM>
 hipError_t launch_step(lbm_handle* h, StepArgs<typename Store<ST>::R>& a) {
     constexpr int TA = LAT == LAT_D2Q9 ? 64 : 32;
-    constexpr int TB = LAT == LAT_D2Q9 ? 1 : (ST == ST_F64 ? 4 : 8);
+    constexpr int TB = LAT == LAT_D2Q9 ? 1 : (ST == ST_F64 ? 4 : LBM_TILE_B);
     a.tiles_a = (h->NA + TA - 1) / TA;
     a.tiles_b = (h->NB + TB - 1) / TB;
     const int tiles = a.tiles_a * a.tiles_b;
@@ -178,7 +167,10 @@ hipError_t launch_step(lbm_handle* h, StepArgs<typename Store<ST>::R>& a) {
     a.chunk = chunk;
     const int nchunks = (h->NCc + chunk - 1) / chunk;
     const int nblk = tiles * nchunks;
-    hipLaunchKernelGGL((k_step<LAT, NC, ST, COLL, MOM, TA, TB>), dim3(nblk), dim3(TA * TB), 0,
+    // own-node populations stay in registers between pull and collision
+    // where three sets fit (one component, 32-bit arithmetic)
+    constexpr bool CARRY = LBM_CARRY && NC == 1 && ST != ST_F64;
+    hipLaunchKernelGGL((k_step<LAT, NC, ST, COLL, MOM, TA, TB, CARRY>), dim3(nblk), dim3(TA * TB), 0,
                        h->stream, a);
     return hipGetLastError();
 }
@@ -191,11 +183,11 @@ hipError_t dispatch_coll(lbm_handle* h, bool mom, StepArgs<typename Store<ST>::R
 }
 
 template <int LAT, int NC>
-hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u) {
+hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u, const Buffers* bufs) {
     switch (h->p.storage) {
         case LBM_STORE_F64: {
             StepArgs<double> a;
-            fill_args(h, a);
+            fill_args(h, a, bufs);
             a.mom_comp = comp;
             a.mom_rho = (double*)rho;
             a.mom_u = (double*)u;
@@ -203,7 +195,7 @@ hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u)
         }
         case LBM_STORE_F32: {
             StepArgs<float> a;
-            fill_args(h, a);
+            fill_args(h, a, bufs);
             a.mom_comp = comp;
             a.mom_rho = (float*)rho;
             a.mom_u = (float*)u;
@@ -211,7 +203,7 @@ hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u)
         }
         case LBM_STORE_F16DEV: {
             StepArgs<float> a;
-            fill_args(h, a);
+            fill_args(h, a, bufs);
             a.mom_comp = comp;
             a.mom_rho = (float*)rho;
             a.mom_u = (float*)u;
@@ -219,7 +211,7 @@ hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u)
         }
         default: {
             StepArgs<float> a;
-            fill_args(h, a);
+            fill_args(h, a, bufs);
             a.mom_comp = comp;
             a.mom_rho = (float*)rho;
             a.mom_u = (float*)u;
@@ -228,14 +220,15 @@ hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u)
     }
 }
 
-hipError_t run_kernel(lbm_handle* h, bool mom, int comp = -1, void* rho = nullptr, void* u = nullptr) {
+hipError_t run_kernel(lbm_handle* h, bool mom, int comp = -1, void* rho = nullptr, void* u = nullptr,
+                      const Buffers* bufs = nullptr) {
     const bool d2 = h->p.lattice == LBM_D2Q9;
     if (d2) {
-        if (h->p.n_comp == 1) return dispatch_store<LAT_D2Q9, 1>(h, mom, comp, rho, u);
-        return dispatch_store<LAT_D2Q9, 2>(h, mom, comp, rho, u);
+        if (h->p.n_comp == 1) return dispatch_store<LAT_D2Q9, 1>(h, mom, comp, rho, u, bufs);
+        return dispatch_store<LAT_D2Q9, 2>(h, mom, comp, rho, u, bufs);
     }
-    if (h->p.n_comp == 1) return dispatch_store<LAT_D3Q19, 1>(h, mom, comp, rho, u);
-    return dispatch_store<LAT_D3Q19, 2>(h, mom, comp, rho, u);
+    if (h->p.n_comp == 1) return dispatch_store<LAT_D3Q19, 1>(h, mom, comp, rho, u, bufs);
+    return dispatch_store<LAT_D3Q19, 2>(h, mom, comp, rho, u, bufs);
 }
 
 // ---------------------------------------------------------------------------
@@ -375,6 +368,8 @@ hipError_t init_store(lbm_handle* h, const void* rho0, const void* u0) {
 }
 
 }  // namespace
+
+hipError_t lbmi::run_step_buffers(lbm_handle* h, const Buffers& b) { return run_kernel(h, false, -1, nullptr, nullptr, &b); }
 
 extern "C" {
 

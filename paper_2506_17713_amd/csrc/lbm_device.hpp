@@ -223,23 +223,40 @@ __device__ __forceinline__ void pull_node(const StepArgs<typename Store<ST>::R>&
     const int dC[3] = {c == 0 ? (NCc - 1) * plane : -plane, 0, c == NCc - 1 ? (1 - NCc) * plane : plane};
     const S* fin = reinterpret_cast<const S*>(P.fin);
     const size_t N = (size_t)P.N;
+    // streaming loads do not depend on the neighbour word, so they issue
+    // together with it; a source that is solid holds no population and its
+    // value is replaced by the bounced one below
+    S v[NC][Q];
+    float rs[NC][Q];
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int o = opp(i);
         const int src = n + dA[1 - L::ea(i)] + dB[1 - L::eb(i)] + dC[1 - L::ec(i)];
-        const bool bb = (i != 0) && ((word >> i) & 1u);
-        const int idx = bb ? n : src;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const S* pi = fin + (size_t)(k * Q + i) * N;
-            const S* po = fin + (size_t)(k * Q + o) * N;
-            const S v = bb ? po[n] : pi[src];
-            if constexpr (SS::DEV) {
-                const float rs = P.rin[(size_t)k * N + idx];
-                f[k][i] = (float)L::w(i) * rs * (1.0f + SS::load(v));
-            } else {
-                f[k][i] = (R)v;
+            v[k][i] = fin[(size_t)(k * Q + i) * N + src];
+            if constexpr (SS::DEV) rs[k][i] = P.rin[(size_t)k * N + src];
+        }
+    });
+    if (word & ~1u) {
+        // halfway bounce-back: f_i(x) = f*_opp(i)(x) when x - e_i is solid
+        sfor<Q - 1>([&](auto I) {
+            constexpr int i = decltype(I)::value + 1;
+            constexpr int o = opp(i);
+            if ((word >> i) & 1u) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    v[k][i] = fin[(size_t)(k * Q + o) * N + n];
+                    if constexpr (SS::DEV) rs[k][i] = P.rin[(size_t)k * N + n];
+                }
             }
+        });
+    }
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            if constexpr (SS::DEV) f[k][i] = (float)L::w(i) * rs[k][i] * (1.0f + SS::load(v[k][i]));
+            else f[k][i] = (R)v[k][i];
         }
     });
 }
@@ -269,7 +286,7 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
 // ---------------------------------------------------------------------------
 // The fused step (MOM = false) or the moment evaluation (MOM = true).
 // ---------------------------------------------------------------------------
-template <int LAT, int NC, int ST, int COLL, bool MOM, int TA, int TB>
+template <int LAT, int NC, int ST, int COLL, bool MOM, int TA, int TB, bool CARRY>
 __global__ void __launch_bounds__(TA* TB)
     k_step(StepArgs<typename Store<ST>::R> P) {
     using L = Lat<LAT>;
@@ -305,7 +322,18 @@ __global__ void __launch_bounds__(TA* TB)
     const int c1 = (c0 + P.chunk < NCc) ? c0 + P.chunk : NCc;
     const bool smallA = NA < RWA, smallB = NB < RWB;
 
+    auto wrap_c = [&](int cp) { return NCc < 5 ? wrap_any(cp, NCc) : wrap_near(cp, NCc); };
+    auto rho_sum = [&](const R(&f)[NC][Q], int k) {
+        R r = f[k][0];
+        sfor<(Q - 1) / 2>([&](auto PI) {
+            constexpr int i = 2 * decltype(PI)::value + 1;
+            r += f[k][i] + f[k][i + 1];
+        });
+        return r;
+    };
+
     // ---- phase 1: pull a plane with halo 2, store rho (solid: -1) ---------
+    // (a) every position of the plane; used where nothing is carried
     auto fill_rho = [&](int cp) {
         const int slot = (cp - c0 + 5) % 5;
         const int c = NCc < 5 ? wrap_any(cp, NCc) : wrap_near(cp, NCc);
@@ -323,12 +351,80 @@ __global__ void __launch_bounds__(TA* TB)
                 R f[NC][Q];
                 pull_node<LAT, ST, NC>(P, n, a, b, c, word, f);
 #pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    R r = 0;
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][idx] = rho_sum(f, k);
+            }
+        }
+    };
+
+    // (b) the thread's own node into registers, kept until its collision two
+    // planes later, then (threads below HALO) one halo position; a halo-2
+    // position (outside the psi halo) only feeds virtual densities and is
+    // pulled only when it has a solid neighbour.  The neighbour words of the
+    // next plane are fetched one plane ahead so that no pull waits for them.
+    const int la_own = tid % TA, lb_own = tid / TA;
+    const int own_idx = (lb_own + H2B) * RWA + la_own + 2;
+    constexpr int HALO = RP - NT;
+    static_assert(!CARRY || HALO <= NT, "one halo position per thread");
+    const bool has_halo = tid < HALO;
+    int h_ra = 0, h_rb = 0;
+    {
+        constexpr int TOP = H2B * RWA;
+        const int h = has_halo ? tid : 0;
+        if (h < TOP) {
+            h_rb = h / RWA;
+            h_ra = h % RWA;
+        } else if (h < 2 * TOP) {
+            h_rb = TB + H2B + (h - TOP) / RWA;
+            h_ra = (h - TOP) % RWA;
+        } else {
+            const int h3 = h - 2 * TOP;
+            h_rb = H2B + h3 / 4;
+            const int c4 = h3 % 4;
+            h_ra = c4 < 2 ? c4 : TA + c4;
+        }
+    }
+    const bool h_outer = h_ra == 0 || h_ra == RWA - 1 || (D3 && (h_rb == 0 || h_rb == RWB - 1));
+    const int h_idx = h_rb * RWA + h_ra;
+    int own_a = a0 + la_own, own_b = b0 + lb_own;
+    own_a = smallA ? wrap_any(own_a, NA) : wrap_near(own_a, NA);
+    own_b = D3 ? (smallB ? wrap_any(own_b, NB) : wrap_near(own_b, NB)) : 0;
+    int h_a = a0 + h_ra - 2, h_b = b0 + h_rb - H2B;
+    h_a = smallA ? wrap_any(h_a, NA) : wrap_near(h_a, NA);
+    h_b = D3 ? (smallB ? wrap_any(h_b, NB) : wrap_near(h_b, NB)) : 0;
+    uint32_t w_own = 0, w_halo = 0;
+    auto fetch_words = [&](int cp) {
+        const int c = wrap_c(cp);
+        w_own = P.nbr[(c * NB + own_b) * NA + own_a];
+        w_halo = has_halo ? P.nbr[(c * NB + h_b) * NA + h_a] : 0u;
+    };
+    auto fill_rho_carry = [&](int cp, R(&fo)[NC][Q]) {
+        const int slot = (cp - c0 + 5) % 5;
+        const int c = wrap_c(cp);
+        const uint32_t wo = w_own, wh = w_halo;
+        fetch_words(cp + 1);
+        {
+            const int n = (c * NB + own_b) * NA + own_a;
+            pull_node<LAT, ST, NC>(P, n, own_a, own_b, c, wo, fo);
+            if (wo & 1u) {
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) r += f[k][i];
-                    s_rho[slot][k][idx] = r;
-                }
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = (R)-1;
+            } else {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = rho_sum(fo, k);
+            }
+        }
+        if (has_halo) {
+            if (wh & 1u) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx] = (R)-1;
+            } else if (h_outer && wh == 0u) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx] = (R)0;  // never read
+            } else {
+                R f[NC][Q];
+                pull_node<LAT, ST, NC>(P, (c * NB + h_b) * NA + h_a, h_a, h_b, c, wh, f);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx] = rho_sum(f, k);
             }
         }
     };
@@ -395,8 +491,8 @@ __global__ void __launch_bounds__(TA* TB)
     };
 
     // ---- phase 3: force, collision + EDM, store (or moments) --------------
-    auto collide = [&](int c) {
-        const int la = tid % TA, lb = tid / TA;
+    auto collide_f = [&](int c, const R(&f)[NC][Q], bool pulled) {
+        const int la = la_own, lb = lb_own;
         const int a = a0 + la, b = b0 + lb;
         if (a >= NA || b >= NB) return;
         const int n = (c * NB + b) * NA + a;
@@ -412,8 +508,7 @@ __global__ void __launch_bounds__(TA* TB)
             }
             return;
         }
-        R f[NC][Q];
-        pull_node<LAT, ST, NC>(P, n, a, b, c, word, f);
+        (void)pulled;
         // moments (Eq. 4); the momentum is summed over differences of opposite
         // populations, which are exact in floating point when the two are
         // within a factor of two of each other (Sterbenz)
@@ -604,21 +699,58 @@ __global__ void __launch_bounds__(TA* TB)
         }
     };
 
+    // re-pull variant: the collision pulls its node again (L2-resident)
+    auto collide = [&](int c) {
+        const int a = a0 + la_own, b = b0 + lb_own;
+        if (a >= NA || b >= NB) return;
+        const int n = (c * NB + b) * NA + a;
+        const uint32_t word = P.nbr[n];
+        R f[NC][Q];
+        if (!(word & 1u)) pull_node<LAT, ST, NC>(P, n, a, b, c, word, f);
+        collide_f(c, f, true);
+    };
+
     // ---- pipeline along c ---------------------------------------------------
     fill_rho(c0 - 2);
     fill_rho(c0 - 1);
-    fill_rho(c0);
-    fill_rho(c0 + 1);
-    __syncthreads();
-    fill_psi(c0 - 1);
-    fill_psi(c0);
-    __syncthreads();
-    for (int c = c0; c < c1; ++c) {
-        fill_rho(c + 2);
+    if constexpr (!CARRY) {
+        fill_rho(c0);
+        fill_rho(c0 + 1);
         __syncthreads();
-        fill_psi(c + 1);
+        fill_psi(c0 - 1);
+        fill_psi(c0);
         __syncthreads();
-        collide(c);
+        for (int c = c0; c < c1; ++c) {
+            fill_rho(c + 2);
+            __syncthreads();
+            fill_psi(c + 1);
+            __syncthreads();
+            collide(c);
+        }
+    } else {
+        // populations of the own node of planes c, c+1, c+2 (set = plane mod 3)
+        R fc0[NC][Q], fc1[NC][Q], fc2[NC][Q];
+        fetch_words(c0);
+        fill_rho_carry(c0, fc0);
+        fill_rho_carry(c0 + 1, fc1);
+        __syncthreads();
+        fill_psi(c0 - 1);
+        fill_psi(c0);
+        __syncthreads();
+        auto stage = [&](int c, R(&cur)[NC][Q], R(&nxt2)[NC][Q]) {
+            fill_rho_carry(c + 2, nxt2);
+            __syncthreads();
+            fill_psi(c + 1);
+            __syncthreads();
+            collide_f(c, cur, false);
+        };
+        for (int c = c0; c < c1; c += 3) {
+            stage(c, fc0, fc2);
+            if (c + 1 >= c1) break;
+            stage(c + 1, fc1, fc0);
+            if (c + 2 >= c1) break;
+            stage(c + 2, fc2, fc1);
+        }
     }
 }
 

@@ -1,0 +1,58 @@
+// Internals of liblbm.so shared by the forward (lbm_api.hip) and adjoint
+// (lbm_adjoint.hip) translation units: workspace layout and the handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+
+#include "lbm.h"
+#include "lbm_device.hpp"
+
+namespace lbmi {
+
+constexpr int kRedBlocks = 1024;  // partial sums of the first reduction pass
+constexpr int kRedThreads = 256;
+constexpr int kStatSlots = 16;    // doubles per partial / in the result
+
+struct Layout {
+    size_t fA, fB, rA, rB, nbr, wet, mrho, mu, uxprev, partial, dstats, total;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+inline int q_of(int lat) { return lat == LBM_D2Q9 ? 9 : 19; }
+inline size_t store_bytes(int st) { return st == LBM_STORE_F64 ? 8 : (st == LBM_STORE_F32 ? 4 : 2); }
+inline size_t real_bytes(int st) { return st == LBM_STORE_F64 ? 8 : 4; }
+inline bool is_dev(int st) { return st == LBM_STORE_F16DEV || st == LBM_STORE_BF16DEV; }
+
+// Explicit population buffers for one launch of the fused step.
+struct Buffers {
+    const void* fin;
+    void* fout;
+    const float* rin;
+    float* rout;
+};
+
+}  // namespace lbmi
+
+struct lbm_handle {
+    lbm_params p;
+    lbmi::Layout lay;
+    hipStream_t stream;
+    char* ws;
+    int N, NA, NB, NCc;
+    int cur;          // 0: state in fA/rA, 1: state in fB/rB
+    int64_t step;
+    int64_t since_check;
+    bool have_prev;
+    int chunk_override;
+};
+
+namespace lbmi {
+// One fused step from b.fin to b.fout (the handle's own buffers are untouched).
+hipError_t run_step_buffers(lbm_handle* h, const Buffers& b);
+// Pointer to the handle's current state buffer.
+inline void* state_ptr(lbm_handle* h) { return h->ws + (h->cur ? h->lay.fB : h->lay.fA); }
+}  // namespace lbmi

@@ -20,7 +20,9 @@ ERRORS = {-1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP", -4: "
           -5: "LBM_ERR_SPACE"}
 STORAGE = {"F64": 0, "F32": 1, "F16DEV": 2, "BF16DEV": 3}
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_moments", "lbm_stats", "lbm_sync",
-           "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_free", "lbm_strerror"]
+           "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_grad_workspace_size", "lbm_grad",
+           "lbm_free", "lbm_strerror"]
+OBSERVABLES = {"saturation": 0, "drho": 1}
 
 
 class LbmError(RuntimeError):
@@ -56,6 +58,14 @@ class LbmStats(C.Structure):
                 "n_fluid": self.n_fluid, "nonfinite": self.nonfinite, "negative": self.negative}
 
 
+class LbmGradReq(C.Structure):
+    _fields_ = [
+        ("observable", C.c_int32), ("nsteps", C.c_int32), ("ckpt_every", C.c_int32),
+        ("reserved", C.c_int32), ("rho_mid", C.c_double), ("delta", C.c_double),
+        ("dL_drho", C.c_void_p), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
+    ]
+
+
 _lib = None
 
 
@@ -76,6 +86,8 @@ def load():
         lib.lbm_state_bytes.argtypes = [vp, C.POINTER(sz)]
         lib.lbm_get_state.argtypes = [vp, vp]
         lib.lbm_set_state.argtypes = [vp, vp]
+        lib.lbm_grad_workspace_size.argtypes = [vp, vp, C.POINTER(sz)]
+        lib.lbm_grad.argtypes = [vp, vp, C.POINTER(C.c_double), vp, C.POINTER(C.c_double)]
         lib.lbm_free.argtypes = [vp]
         lib.lbm_free.restype = None
         lib.lbm_strerror.argtypes = [C.c_int]
@@ -197,6 +209,28 @@ class Solver:
     def set_state(self, buf) -> None:
         assert buf.numel() == self.state_bytes()
         _check("lbm_set_state", self.lib.lbm_set_state(self.h, buf.data_ptr()))
+
+    def grad(self, nsteps: int, ckpt_every: int, observable: str = "saturation", rho_mid: float = 0.0,
+             delta: float = 1.0, dL_drho=None):
+        """Run nsteps from the current state and back-propagate (lbm_grad).
+        Returns (L, dL/dwet as a device float64 tensor [N], dL/dT)."""
+        t = self.torch
+        r = LbmGradReq()
+        r.observable = OBSERVABLES[observable]
+        r.nsteps, r.ckpt_every = int(nsteps), int(ckpt_every)
+        r.rho_mid, r.delta = float(rho_mid), float(delta)
+        if dL_drho is not None:
+            assert dL_drho.dtype == self.real and dL_drho.is_contiguous()
+            r.dL_drho = dL_drho.data_ptr()
+        size = C.c_size_t()
+        _check("lbm_grad_workspace_size", self.lib.lbm_grad_workspace_size(self.h, C.byref(r), C.byref(size)))
+        ws = t.empty(size.value, dtype=t.uint8, device=self.device)
+        r.ws, r.ws_bytes = ws.data_ptr(), size.value
+        dwet = t.empty(self.w.N, dtype=t.float64, device=self.device)
+        L, dT = C.c_double(), C.c_double()
+        _check("lbm_grad", self.lib.lbm_grad(self.h, C.byref(r), C.byref(L), dwet.data_ptr(), C.byref(dT)))
+        del ws
+        return L.value, dwet, dT.value
 
     def close(self) -> None:
         if getattr(self, "h", None):

@@ -1,0 +1,221 @@
+"""The hand-written adjoint (lbm_grad) against derivatives the oracle gives
+independently: complex-step differentiation of the FP64 oracle (exact to
+rounding: an imaginary perturbation of one wetting parameter or of T carried
+through every step) and central finite differences of the GPU forward solver
+in FP64 at the full 128^3 / 1000-step adjoint workload.
+
+Observable: smooth non-wetting (vapour) saturation of the final density,
+S = (1/N_fluid) sum_fluid sigma((rho_mid - rho) / delta), delta = 0.05 (rho_l - rho_v)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2506_17713_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.environ.get("LBM_TEST_REPORT", "gpurun_out/parity_report.jsonl")
+
+
+def _report(rec):
+    try:
+        os.makedirs(os.path.dirname(OUT), exist_ok=True)
+        with open(OUT, "a") as fh:
+            fh.write(json.dumps(rec) + "\n")
+    except OSError:
+        pass
+
+
+def sat_params(w):
+    rl, rv = w.rho_max[0], w.rho_min[0]
+    return 0.5 * (rl + rv), 0.05 * (rl - rv)
+
+
+def oracle_saturation(st, fluid, rho_mid, delta):
+    r = st.fields()["rho"][0]
+    z = (rho_mid - r[fluid]) / delta
+    return (1.0 / (1.0 + np.exp(-z))).sum() / fluid.sum()
+
+
+def oracle_cstep(oracle_mod, w, solid, rho, steps, voxels, wet=None):
+    """Complex-step derivatives dS/dwet[voxel] and dS/dT."""
+    rho_mid, delta = sat_params(w)
+    fluid = solid.reshape(-1) == 0
+    base = np.full((1, w.N), w.wet[0], dtype=np.complex128) if wet is None else wet.astype(np.complex128).reshape(1, -1)
+    h = 1e-30
+    out = []
+    for v in voxels:
+        ww = base.copy()
+        ww[0, v] += 1j * h
+        st = oracle_mod.State(w, solid, rho, wet=ww, cstep=True)
+        st.step(steps)
+        out.append(oracle_saturation(st, fluid, rho_mid, delta).imag / h)
+    st = oracle_mod.State(w, solid, rho, wet=base, cstep=True, T_im=h)
+    st.step(steps)
+    dT = oracle_saturation(st, fluid, rho_mid, delta).imag / h
+    st0 = oracle_mod.State(w, solid, rho, wet=base.real)
+    st0.step(steps)
+    S = oracle_saturation(st0, fluid, rho_mid, delta)
+    return S, np.array(out), dT
+
+
+def gpu_grad(w, solid, rho, steps, ckpt, wet=None):
+    from paper_2506_17713_amd import lbm
+
+    rho_mid, delta = sat_params(w)
+    sol = lbm.Solver(w, solid, rho, wet=wet)
+    L, dwet, dT = sol.grad(steps, ckpt, "saturation", rho_mid, delta)
+    g = dwet.cpu().numpy()
+    sol.close()
+    return L, g, dT
+
+
+def boundary_voxels(solid, count, seed):
+    """Solid voxels with a fluid face neighbour (periodic), seeded choice."""
+    s = solid.astype(bool)
+    touch = np.zeros_like(s)
+    for ax in range(3):
+        for sh in (-1, 1):
+            touch |= np.roll(~s, sh, axis=ax)
+    cand = np.flatnonzero((s & touch).reshape(-1))
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(cand, size=min(count, len(cand)), replace=False))
+
+
+def small_sessile(storage, coll="MRT", mode="PHI", val=1.05):
+    c = inputs.load_coexistence()["CS"]["0.8"]
+    shape = (12, 14, 16)
+    w = inputs.Workload("adj_sessile", "D3Q19", shape, collision=coll, storage=storage,
+                        eos_T=(c["T"],) * 2, A=(c["A"],) * 2, wet_mode=(mode, mode), wet=(val, val),
+                        rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2)
+    solid = inputs.walls(shape, "z", (0, 11))
+    rho = inputs.droplet(shape, (8.0, 7.0, 4.0), 4.5, 3, c["rho_l"], c["rho_v"])[None]
+    return w, solid, rho
+
+
+@pytest.mark.parametrize("coll,mode,val", [("MRT", "PHI", 1.05), ("BGK", "DRHO", 0.01)])
+def test_adjoint_f64_matches_oracle_complex_step(oracle_mod, coll, mode, val):
+    w, solid, rho = small_sessile("F64", coll, mode, val)
+    steps, ckpt = 40, 7
+    # wall voxels under and around the droplet
+    vox = [(0 * 14 + 7) * 16 + 8, (0 * 14 + 7) * 16 + 12, (0 * 14 + 3) * 16 + 8, (0 * 14 + 10) * 16 + 3,
+           (11 * 14 + 7) * 16 + 8]
+    print(f"case adjoint F64 {coll} {mode} {w.shape} {steps} steps", flush=True)
+    L, g, dT = gpu_grad(w, solid, rho, steps, ckpt)
+    S, go, dTo = oracle_cstep(oracle_mod, w, solid, rho, steps, vox)
+    rel = np.abs(g[vox] - go).max() / np.abs(go).max()
+    relT = abs(dT - dTo) / abs(dTo)
+    _report({"case": f"adjoint_f64_{coll}_{mode}", "L": L, "L_oracle": S, "rel_err_dwet": rel,
+             "rel_err_dT": relT, "dwet_oracle": go.tolist(), "dT_oracle": dTo})
+    print(L, S, rel, relT, flush=True)
+    assert abs(L - S) < 1e-12
+    assert rel < 1e-8 and relT < 1e-8
+    # gradient lives only on solid nodes that touch fluid
+    assert np.all(g[solid.reshape(-1) == 0] == 0.0)
+
+
+def test_adjoint_f64_d2q9(oracle_mod):
+    c = inputs.load_coexistence()["CS"]["0.7"]
+    shape = (1, 30, 40)
+    w = inputs.Workload("adj2d", "D2Q9", shape, collision="MRT", storage="F64", eos_T=(c["T"],) * 2,
+                        A=(c["A"],) * 2, wet_mode=("PHI", "PHI"), wet=(1.05, 1.05),
+                        rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2)
+    solid = inputs.walls(shape, "y", (0, 29))
+    rho = inputs.droplet(shape, (20.0, 1.0, 0.0), 9, 3, c["rho_l"], c["rho_v"])[None]
+    vox = [20, 27, 12, 31, 29 * 40 + 20]
+    L, g, dT = gpu_grad(w, solid, rho, 60, 16)
+    S, go, dTo = oracle_cstep(oracle_mod, w, solid, rho, 60, vox)
+    rel = np.abs(g[vox] - go).max() / np.abs(go).max()
+    assert rel < 1e-8 and abs(dT - dTo) / abs(dTo) < 1e-8
+
+
+def test_adjoint_f32_matches_oracle_on_pack_crop(oracle_mod):
+    """FP32 adjoint on a 32^3 crop of the adjoint sphere pack (periodic), 150
+    steps, against the FP64 oracle's complex-step derivative."""
+    w, solid, rho = inputs.adjoint_pack(shape=(32, 32, 32), storage="F32", steps=150)
+    vox = boundary_voxels(solid, 6, seed=2)
+    L, g, dT = gpu_grad(w, solid, rho, 150, 50)
+    S, go, dTo = oracle_cstep(oracle_mod, w.with_(storage="F64"), solid, rho, 150, vox)
+    rel = np.abs(g[vox] - go).max() / np.abs(go).max()
+    relT = abs(dT - dTo) / abs(dTo)
+    _report({"case": "adjoint_f32_pack32", "L": L, "L_oracle": S, "rel_err_dwet": rel, "rel_err_dT": relT})
+    print(L, S, rel, relT, flush=True)
+    assert abs(L - S) < 1e-5
+    assert rel < 1e-3 and relT < 1e-3
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    w, solid, rho = small_sessile("F32")
+    a = gpu_grad(w, solid, rho, 50, 50)
+    b = gpu_grad(w, solid, rho, 50, 7)
+    c = gpu_grad(w, solid, rho, 50, 1)
+    assert a[0] == b[0] == c[0]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[1], c[1])
+    assert a[2] == b[2] == c[2]
+
+
+def test_autograd_function_backward():
+    import torch
+
+    from paper_2506_17713_amd.autograd import AdjointSetup, NonWettingSaturation
+
+    w, solid, rho = small_sessile("F64")
+    rho_mid, delta = sat_params(w)
+    setup = AdjointSetup(w, solid, rho, nsteps=30, ckpt_every=10, rho_mid=rho_mid, delta=delta)
+    wet = torch.full(w.shape, 1.05, dtype=torch.float64, requires_grad=True)
+    T = torch.tensor(w.eos_T[0], dtype=torch.float64, requires_grad=True)
+    S = NonWettingSaturation.apply(wet, T, setup)
+    (2.0 * S).backward()
+    L, g, dT = gpu_grad(w, solid, rho, 30, 10)
+    assert float(S) == pytest.approx(L, abs=1e-14)
+    assert np.allclose(wet.grad.numpy().reshape(-1), 2.0 * g, rtol=0, atol=0)
+    assert float(T.grad) == pytest.approx(2.0 * dT, rel=1e-14)
+
+
+def test_adjoint_pack128_vs_finite_differences():
+    """The adjoint workload: 128^3 sphere pack (porosity 0.4, radii 6-14,
+    seed 1), CS at T_r = 0.8, MRT, 1000 steps with a checkpoint every 100.
+    FP32 adjoint gradients against central differences (h = 1e-3 in the
+    wetting parameter and in T_r) of the FP64 GPU forward solver at 20 seeded
+    boundary voxels and T."""
+    from paper_2506_17713_amd import lbm
+
+    steps, ckpt, h = 1000, 100, 1e-3
+    w, solid, rho = inputs.adjoint_pack(storage="F32")
+    print("case adjoint 128^3 FD", flush=True)
+    L, g, dT = gpu_grad(w, solid, rho, steps, ckpt)
+    rho_mid, delta = sat_params(w)
+    w64 = w.with_(storage="F64")
+    fluid = solid.reshape(-1) == 0
+
+    def S_of(wet=None, T=None):
+        ww = w64 if T is None else w64.with_(eos_T=(T, T))
+        sol = lbm.Solver(ww, solid, rho, wet=wet)
+        sol.step(steps)
+        r, _ = sol.moments_numpy(-1)
+        sol.close()
+        z = (rho_mid - r[fluid]) / delta
+        return (1.0 / (1.0 + np.exp(-z))).sum() / fluid.sum()
+
+    # voxels whose virtual density stays off the limiter: walls next to vapour
+    vox = boundary_voxels(solid, 60, seed=7)
+    x = vox % w.shape[2]
+    vox = vox[x > w.shape[2] // 2 + 8][:20]
+    base = np.full((1, w.N), w.wet[0])
+    fd = []
+    for v in vox:
+        p, m = base.copy(), base.copy()
+        p[0, v] += h
+        m[0, v] -= h
+        fd.append((S_of(wet=p) - S_of(wet=m)) / (2 * h))
+    fd = np.array(fd)
+    Tc = inputs.load_coexistence()["CS"]["Tc"]
+    dT_fd = (S_of(T=w.eos_T[0] + h * Tc) - S_of(T=w.eos_T[0] - h * Tc)) / (2 * h * Tc)
+    rel = np.abs(g[vox] - fd).max() / np.abs(fd).max()
+    relT = abs(dT - dT_fd) / abs(dT_fd)
+    _report({"case": "adjoint_pack128_fd", "S": L, "n_vox": len(vox), "rel_err_dwet_maxnorm": rel,
+             "rel_err_dTr": relT, "dT": dT, "dT_fd": dT_fd, "dwet_fd_max": float(np.abs(fd).max())})
+    print(L, rel, relT, flush=True)
+    assert rel < 1e-2 and relT < 1e-2
