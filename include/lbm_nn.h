@@ -1,0 +1,81 @@
+/*
+ * C-ABI of the convolutional surrogate kernels in liblbm.so.
+ *
+ * The surrogate is a 3-D encoder-decoder that maps a pore-space mask to the
+ * steady single-phase velocity field; its prediction warm-starts the solver
+ * (f = f^eq(1, u_pred)) when computing permeability from Darcy's law, the
+ * workflow the paper runs with a cold start (Sec. 3.4.1, 50,000 steps to
+ * steady state).  These are its training and inference kernels.
+ *
+ * Conventions
+ *   - Activations are FP32 device arrays [C][D][H][W] (W fastest).
+ *   - Every convolution is 3x3x3, stride 1, with periodic wrap (the pore
+ *     geometries are periodic), computed on MFMA matrix cores: BF16 inputs
+ *     with FP32 accumulation (prec = LBM_NN_BF16) or FP32 inputs
+ *     (prec = LBM_NN_FP32).
+ *   - Weights are FP32 [C_out][C_in][27] with tap t = 9 dz + 3 dy + dx
+ *     (dz, dy, dx in 0..2, offset -1); they are packed once per update with
+ *     lbm_nn_pack before use.
+ *   - All work is enqueued on the given hipStream_t (asynchronous); pointers
+ *     are device pointers owned by the caller.  Returns 0 or LBM_ERR_ARG /
+ *     LBM_ERR_HIP (include/lbm.h).
+ */
+#ifndef PAPER_2506_17713_LBM_NN_H
+#define PAPER_2506_17713_LBM_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { LBM_NN_BF16 = 0, LBM_NN_FP32 = 1 };
+
+/* Number of 32-bit words of the packed weights of a (c_out, c_in) layer. */
+size_t lbm_nn_packed_words(int c_out, int c_in);
+
+/* Pack W [c_out][c_in][27] for lbm_nn_conv.  transpose = 1 packs the weights
+ * of the data-gradient convolution (channels swapped, taps mirrored), so that
+ * lbm_nn_conv(dY, packed_T) gives dL/dX. */
+int lbm_nn_pack(const float* W, int c_out, int c_in, int transpose, int prec, uint32_t* packed, void* stream);
+
+/* Y[co] = act(bias[co] + sum_ci sum_t W[co][ci][t] X[ci][p + off(t)]) + skip[co]
+ * act = max(0, .) when relu != 0; bias and skip may be NULL. */
+int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* bias, const float* skip,
+                float* Y, int c_out, int D, int H, int W, int relu, int prec, void* stream);
+
+/* dW[co][ci][t] = sum_p dY[co][p] X[ci][p + off(t)] (overwrites dW).
+ * partial: device scratch of lbm_nn_wgrad_partial_words(c_out, c_in, D, H, W) floats. */
+size_t lbm_nn_wgrad_partial_words(int c_out, int c_in, int D, int H, int W);
+int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, int H, int W, float* dW,
+                 float* partial, int prec, void* stream);
+
+/* db[c] = sum_p dY[c][p] (overwrites). */
+int lbm_nn_bias_grad(const float* dY, int c, int64_t P, float* db, void* stream);
+/* dY[i] *= (Y[i] > 0) */
+int lbm_nn_relu_bwd(const float* Y, float* dY, int64_t n, void* stream);
+/* y[i] += x[i] */
+int lbm_nn_add(float* y, const float* x, int64_t n, void* stream);
+/* 2x2x2 average pooling of X [c][D][H][W] into Y [c][D/2][H/2][W/2] and its
+ * adjoint dX = dY / 8 spread over the children (accumulate: dX += ...). */
+int lbm_nn_pool(const float* X, int c, int D, int H, int W, float* Y, void* stream);
+int lbm_nn_pool_bwd(const float* dY, int c, int D, int H, int W, float* dX, int accumulate, void* stream);
+/* Nearest 2x upsampling of X [c][D][H][W] into Y [c][2D][2H][2W] and its
+ * adjoint dX = sum over the 8 children of dY. */
+int lbm_nn_up(const float* X, int c, int D, int H, int W, float* Y, void* stream);
+int lbm_nn_up_bwd(const float* dY, int c, int D, int H, int W, float* dX, void* stream);
+/* Masked mean squared error over c channels: L = sum_{c,p} mask[p] (Y - T)^2 / (c sum_p mask[p]).
+ * loss: device double[2 + 512]; loss[0] = L, loss[1] = sum_p mask[p], the rest
+ * is scratch.  dY = dL/dY (may be NULL). */
+int lbm_nn_mse(const float* Y, const float* T, const float* mask, int c, int64_t P, double* loss, float* dY,
+               void* stream);
+/* Adam update (Kingma & Ba) of n parameters at step t >= 1. */
+int lbm_nn_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                float eps, int t, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2506_17713_LBM_NN_H */

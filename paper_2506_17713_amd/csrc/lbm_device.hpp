@@ -286,8 +286,11 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
 // ---------------------------------------------------------------------------
 // The fused step (MOM = false) or the moment evaluation (MOM = true).
 // ---------------------------------------------------------------------------
+#ifndef LBM_WAVES_PER_EU
+#define LBM_WAVES_PER_EU 1
+#endif
 template <int LAT, int NC, int ST, int COLL, bool MOM, int TA, int TB, bool CARRY>
-__global__ void __launch_bounds__(TA* TB)
+__global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
     k_step(StepArgs<typename Store<ST>::R> P) {
     using L = Lat<LAT>;
     using SS = Store<ST>;
@@ -333,74 +336,59 @@ __global__ void __launch_bounds__(TA* TB)
     };
 
     // ---- phase 1: pull a plane with halo 2, store rho (solid: -1) ---------
-    // (a) every position of the plane; used where nothing is carried
-    auto fill_rho = [&](int cp) {
-        const int slot = (cp - c0 + 5) % 5;
-        const int c = NCc < 5 ? wrap_any(cp, NCc) : wrap_near(cp, NCc);
-        for (int idx = tid; idx < RP; idx += NT) {
-            const int ra = idx % RWA, rb = idx / RWA;
-            int a = a0 + ra - 2, b = b0 + rb - H2B;
-            a = smallA ? wrap_any(a, NA) : wrap_near(a, NA);
-            b = D3 ? (smallB ? wrap_any(b, NB) : wrap_near(b, NB)) : 0;
-            const int n = (c * NB + b) * NA + a;
-            const uint32_t word = P.nbr[n];
-            if (word & 1u) {
-#pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][idx] = (R)-1;
-            } else {
-                R f[NC][Q];
-                pull_node<LAT, ST, NC>(P, n, a, b, c, word, f);
-#pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][idx] = rho_sum(f, k);
-            }
-        }
-    };
-
-    // (b) the thread's own node into registers, kept until its collision two
-    // planes later, then (threads below HALO) one halo position; a halo-2
-    // position (outside the psi halo) only feeds virtual densities and is
-    // pulled only when it has a solid neighbour.  The neighbour words of the
-    // next plane are fetched one plane ahead so that no pull waits for them.
+    // Each thread pulls its own node (kept in registers until its collision
+    // two planes later when CARRY) and HPT halo positions.  A halo-2 position
+    // (outside the psi halo) only feeds virtual densities and is pulled only
+    // when it has a solid neighbour.  The neighbour words of the next plane
+    // are fetched one plane ahead so that no pull waits for them.
     const int la_own = tid % TA, lb_own = tid / TA;
     const int own_idx = (lb_own + H2B) * RWA + la_own + 2;
     constexpr int HALO = RP - NT;
-    static_assert(!CARRY || HALO <= NT, "one halo position per thread");
-    const bool has_halo = tid < HALO;
-    int h_ra = 0, h_rb = 0;
-    {
-        constexpr int TOP = H2B * RWA;
-        const int h = has_halo ? tid : 0;
-        if (h < TOP) {
-            h_rb = h / RWA;
-            h_ra = h % RWA;
-        } else if (h < 2 * TOP) {
-            h_rb = TB + H2B + (h - TOP) / RWA;
-            h_ra = (h - TOP) % RWA;
-        } else {
-            const int h3 = h - 2 * TOP;
-            h_rb = H2B + h3 / 4;
-            const int c4 = h3 % 4;
-            h_ra = c4 < 2 ? c4 : TA + c4;
-        }
-    }
-    const bool h_outer = h_ra == 0 || h_ra == RWA - 1 || (D3 && (h_rb == 0 || h_rb == RWB - 1));
-    const int h_idx = h_rb * RWA + h_ra;
+    constexpr int HPT = (HALO + NT - 1) / NT;
     int own_a = a0 + la_own, own_b = b0 + lb_own;
     own_a = smallA ? wrap_any(own_a, NA) : wrap_near(own_a, NA);
     own_b = D3 ? (smallB ? wrap_any(own_b, NB) : wrap_near(own_b, NB)) : 0;
-    int h_a = a0 + h_ra - 2, h_b = b0 + h_rb - H2B;
-    h_a = smallA ? wrap_any(h_a, NA) : wrap_near(h_a, NA);
-    h_b = D3 ? (smallB ? wrap_any(h_b, NB) : wrap_near(h_b, NB)) : 0;
-    uint32_t w_own = 0, w_halo = 0;
+    int h_idx[HPT], h_a[HPT], h_b[HPT];
+    bool h_on[HPT], h_outer[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        constexpr int TOP = H2B * RWA;
+        const int h = tid + j * NT;
+        h_on[j] = h < HALO;
+        const int hh = h_on[j] ? h : 0;
+        int ra, rb;
+        if (hh < TOP) {
+            rb = hh / RWA;
+            ra = hh % RWA;
+        } else if (hh < 2 * TOP) {
+            rb = TB + H2B + (hh - TOP) / RWA;
+            ra = (hh - TOP) % RWA;
+        } else {
+            const int h3 = hh - 2 * TOP;
+            rb = H2B + h3 / 4;
+            const int c4 = h3 % 4;
+            ra = c4 < 2 ? c4 : TA + c4;
+        }
+        h_outer[j] = ra == 0 || ra == RWA - 1 || (D3 && (rb == 0 || rb == RWB - 1));
+        h_idx[j] = rb * RWA + ra;
+        int ha = a0 + ra - 2, hb = b0 + rb - H2B;
+        h_a[j] = smallA ? wrap_any(ha, NA) : wrap_near(ha, NA);
+        h_b[j] = D3 ? (smallB ? wrap_any(hb, NB) : wrap_near(hb, NB)) : 0;
+    }
+    uint32_t w_own = 0, w_halo[HPT];
     auto fetch_words = [&](int cp) {
         const int c = wrap_c(cp);
         w_own = P.nbr[(c * NB + own_b) * NA + own_a];
-        w_halo = has_halo ? P.nbr[(c * NB + h_b) * NA + h_a] : 0u;
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) w_halo[j] = h_on[j] ? P.nbr[(c * NB + h_b[j]) * NA + h_a[j]] : 0u;
     };
-    auto fill_rho_carry = [&](int cp, R(&fo)[NC][Q]) {
+    auto fill_rho = [&](int cp, R(&fo)[NC][Q]) {
         const int slot = (cp - c0 + 5) % 5;
         const int c = wrap_c(cp);
-        const uint32_t wo = w_own, wh = w_halo;
+        const uint32_t wo = w_own;
+        uint32_t wh[HPT];
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) wh[j] = w_halo[j];
         fetch_words(cp + 1);
         {
             const int n = (c * NB + own_b) * NA + own_a;
@@ -413,18 +401,20 @@ __global__ void __launch_bounds__(TA* TB)
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = rho_sum(fo, k);
             }
         }
-        if (has_halo) {
-            if (wh & 1u) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx] = (R)-1;
-            } else if (h_outer && wh == 0u) {
+        for (int j = 0; j < HPT; ++j) {
+            if (!h_on[j]) continue;
+            if (wh[j] & 1u) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx] = (R)0;  // never read
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = (R)-1;
+            } else if (h_outer[j] && wh[j] == 0u) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = (R)0;  // never read
             } else {
                 R f[NC][Q];
-                pull_node<LAT, ST, NC>(P, (c * NB + h_b) * NA + h_a, h_a, h_b, c, wh, f);
+                pull_node<LAT, ST, NC>(P, (c * NB + h_b[j]) * NA + h_a[j], h_a[j], h_b[j], c, wh[j], f);
 #pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx] = rho_sum(f, k);
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = rho_sum(f, k);
             }
         }
     };
@@ -699,57 +689,40 @@ __global__ void __launch_bounds__(TA* TB)
         }
     };
 
-    // re-pull variant: the collision pulls its node again (L2-resident)
-    auto collide = [&](int c) {
-        const int a = a0 + la_own, b = b0 + lb_own;
-        if (a >= NA || b >= NB) return;
-        const int n = (c * NB + b) * NA + a;
-        const uint32_t word = P.nbr[n];
-        R f[NC][Q];
-        if (!(word & 1u)) pull_node<LAT, ST, NC>(P, n, a, b, c, word, f);
-        collide_f(c, f, true);
-    };
-
     // ---- pipeline along c ---------------------------------------------------
-    fill_rho(c0 - 2);
-    fill_rho(c0 - 1);
-    if constexpr (!CARRY) {
-        fill_rho(c0);
-        fill_rho(c0 + 1);
+    // Iteration it pulls plane it+2, evaluates psi of plane it+1 and collides
+    // plane it; the first four iterations only fill the rings.  One loop body
+    // keeps the code small enough for the instruction cache.
+    R fc0[NC][Q], fc1[NC][Q], fc2[NC][Q];
+    fetch_words(c0 - 2);
+#pragma nounroll
+    for (int it = c0 - 4; it < c1; ++it) {
+        fill_rho(it + 2, fc2);
         __syncthreads();
-        fill_psi(c0 - 1);
-        fill_psi(c0);
+        if (it + 1 >= c0 - 1) fill_psi(it + 1);
         __syncthreads();
-        for (int c = c0; c < c1; ++c) {
-            fill_rho(c + 2);
-            __syncthreads();
-            fill_psi(c + 1);
-            __syncthreads();
-            collide(c);
+        if (it >= c0) {
+            if constexpr (CARRY) {
+                collide_f(it, fc0, false);
+            } else {
+                // re-pull the own node (L2-resident since its ring pull)
+                const int a = a0 + la_own, b = b0 + lb_own;
+                if (a < NA && b < NB) {
+                    const int n = (it * NB + b) * NA + a;
+                    const uint32_t word = P.nbr[n];
+                    if (!(word & 1u)) pull_node<LAT, ST, NC>(P, n, a, b, it, word, fc0);
+                    collide_f(it, fc0, true);
+                }
+            }
         }
-    } else {
-        // populations of the own node of planes c, c+1, c+2 (set = plane mod 3)
-        R fc0[NC][Q], fc1[NC][Q], fc2[NC][Q];
-        fetch_words(c0);
-        fill_rho_carry(c0, fc0);
-        fill_rho_carry(c0 + 1, fc1);
-        __syncthreads();
-        fill_psi(c0 - 1);
-        fill_psi(c0);
-        __syncthreads();
-        auto stage = [&](int c, R(&cur)[NC][Q], R(&nxt2)[NC][Q]) {
-            fill_rho_carry(c + 2, nxt2);
-            __syncthreads();
-            fill_psi(c + 1);
-            __syncthreads();
-            collide_f(c, cur, false);
-        };
-        for (int c = c0; c < c1; c += 3) {
-            stage(c, fc0, fc2);
-            if (c + 1 >= c1) break;
-            stage(c + 1, fc1, fc0);
-            if (c + 2 >= c1) break;
-            stage(c + 2, fc2, fc1);
+        if constexpr (CARRY) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    fc0[k][i] = fc1[k][i];
+                    fc1[k][i] = fc2[k][i];
+                }
         }
     }
 }

@@ -1,0 +1,451 @@
+// Kernels of the 3-D convolutional surrogate (include/lbm_nn.h).
+//
+// Convolution as an implicit GEMM on the MFMA matrix cores:
+//   Y[co][p] = sum_k A[co][k] B[k][p],  k = (tap, ci),  B[k][p] = X[ci][p + off(tap)]
+// A wave owns a 32 (co) x 32 (positions) tile and walks K in steps of 8
+// (v_mfma_f32_32x32x8_bf16) or 2 (v_mfma_f32_32x32x2_f32).  Operand lane
+// layout of these instructions: lane l holds A[l % 32][k0 + l / 32 * kw + j]
+// and B[k0 + l / 32 * kw + j][l % 32] (kw = 4 for bf16, 1 for f32), and the
+// accumulator element v of lane l is D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+// Weight gradients are the GEMM dW[co][(ci,tap)] = sum_p dY[co][p] X[ci][p+off]
+// with positions as the reduction dimension, split into chunks whose partial
+// tiles are summed in a fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm.h"
+#include "lbm_nn.h"
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ short f2bf(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__host__ __device__ inline int cin_pad_of(int cin, int prec) { return prec == LBM_NN_BF16 ? (cin + 7) / 8 * 8 : (cin + 1) / 2 * 2; }
+__host__ __device__ inline int cout_pad_of(int cout) { return (cout + 31) / 32 * 32; }
+
+__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// packed layout: bf16  [tap][cin_pad/4][cout_pad][4] (two 32-bit words per entry)
+//                fp32  [tap][cin_pad][cout_pad]
+__global__ void k_pack(const float* __restrict__ W, int cout, int cin, int transpose, int prec,
+                       uint32_t* __restrict__ out) {
+    // logical layer after an optional transpose: (co', ci') = (ci, co), tap mirrored
+    const int lo = transpose ? cin : cout, li = transpose ? cout : cin;
+    const int cip = cin_pad_of(li, prec), cop = cout_pad_of(lo);
+    const int total = 27 * cip * cop;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int co = idx % cop;
+    const int ci = (idx / cop) % cip;
+    const int tap = idx / (cop * cip);
+    float v = 0.0f;
+    if (co < lo && ci < li) {
+        v = transpose ? W[((size_t)ci * cin + co) * 27 + (26 - tap)] : W[((size_t)co * cin + ci) * 27 + tap];
+    }
+    if (prec == LBM_NN_BF16) {
+        const int cg = ci / 4, j = ci % 4;
+        short* o = reinterpret_cast<short*>(out);
+        o[(((size_t)tap * (cip / 4) + cg) * cop + co) * 4 + j] = f2bf(v);
+    } else {
+        reinterpret_cast<float*>(out)[((size_t)tap * cip + ci) * cop + co] = v;
+    }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256)
+    k_conv(const float* __restrict__ X, int cin, const uint32_t* __restrict__ packed, const float* __restrict__ bias,
+           const float* __restrict__ skip, float* __restrict__ Y, int cout, int D, int H, int W, int relu) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int P = D * H * W;
+    const int p = (blockIdx.x * 4 + wave) * 32 + (lane & 31);
+    const bool pok = p < P;
+    const int pp = pok ? p : 0;
+    const int x = pp % W, y = (pp / W) % H, z = pp / (W * H);
+    const int co0 = blockIdx.y * 32;
+    const int kq = lane >> 5;
+    const int cip = cin_pad_of(cin, PREC), cop = cout_pad_of(cout);
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    for (int tap = 0; tap < 27; ++tap) {
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const int q = (wrapc(z + dz, D) * H + wrapc(y + dy, H)) * W + wrapc(x + dx, W);
+        if constexpr (PREC == LBM_NN_BF16) {
+            const bf16x4* wp = reinterpret_cast<const bf16x4*>(packed);
+            for (int c8 = 0; c8 < cip; c8 += 8) {
+                const bf16x4 a = wp[((size_t)tap * (cip / 4) + c8 / 4 + kq) * cop + co0 + (lane & 31)];
+                bf16x4 b;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ci = c8 + 4 * kq + j;
+                    b[j] = (pok && ci < cin) ? f2bf(X[(size_t)ci * P + q]) : (short)0;
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            }
+        } else {
+            const float* wp = reinterpret_cast<const float*>(packed);
+            for (int c2 = 0; c2 < cip; c2 += 2) {
+                const int ci = c2 + kq;
+                const float a = wp[((size_t)tap * cip + ci) * cop + co0 + (lane & 31)];
+                const float b = (pok && ci < cin) ? X[(size_t)ci * P + q] : 0.0f;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+            }
+        }
+    }
+    if (!pok) return;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
+        if (co < cout) {
+            float r = acc[v] + (bias ? bias[co] : 0.0f);
+            if (relu) r = r > 0.0f ? r : 0.0f;
+            if (skip) r += skip[(size_t)co * P + p];
+            Y[(size_t)co * P + p] = r;
+        }
+    }
+}
+
+// Weight gradient partial tiles: one wave per (co block, n block, position chunk),
+// n = ci * 27 + tap.
+template <int PREC>
+__global__ void __launch_bounds__(64)
+    k_wgrad(const float* __restrict__ X, int cin, const float* __restrict__ dY, int cout, int D, int H, int W,
+            int chunk, float* __restrict__ partial) {
+    const int lane = threadIdx.x;
+    const int P = D * H * W;
+    const int co0 = blockIdx.x * 32, n0 = blockIdx.y * 32, ch = blockIdx.z;
+    const int kq = lane >> 5;
+    const int NN = cin * 27;
+    const int m = co0 + (lane & 31);  // A row (co) of this lane
+    const int n = n0 + (lane & 31);   // B column ((ci, tap)) of this lane
+    const bool mok = m < cout, nok = n < NN;
+    const int ci = nok ? n / 27 : 0, tap = nok ? n % 27 : 0;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int p0 = ch * chunk, p1 = (p0 + chunk < P) ? p0 + chunk : P;
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    constexpr int KW = PREC == LBM_NN_BF16 ? 4 : 1;
+    constexpr int KS = 2 * KW;
+    for (int pk = p0; pk < p1; pk += KS) {
+        float av[KW], bv[KW];
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+            const int p = pk + kq * KW + j;
+            const bool ok = p < p1;
+            const int pp = ok ? p : p0;
+            av[j] = (ok && mok) ? dY[(size_t)m * P + pp] : 0.0f;
+            const int x = pp % W, y = (pp / W) % H, z = pp / (W * H);
+            const int q = (wrapc(z + dz, D) * H + wrapc(y + dy, H)) * W + wrapc(x + dx, W);
+            bv[j] = (ok && nok) ? X[(size_t)ci * P + q] : 0.0f;
+        }
+        if constexpr (PREC == LBM_NN_BF16) {
+            bf16x4 a, b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                a[j] = f2bf(av[j]);
+                b[j] = f2bf(bv[j]);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        } else {
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bv[0], acc, 0, 0, 0);
+        }
+    }
+    // partial[ch][co][n] over the full (cout x NN) extent
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
+        const int nn = n0 + (lane & 31);
+        if (co < cout && nn < NN) partial[((size_t)ch * cout + co) * NN + nn] = acc[v];
+    }
+}
+
+__global__ void k_chunk_sum(const float* __restrict__ partial, int nchunk, int64_t n, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int c = 0; c < nchunk; ++c) s += partial[(size_t)c * n + i];
+    out[i] = s;
+}
+
+__global__ void __launch_bounds__(256) k_bias_grad(const float* __restrict__ dY, int64_t P, float* __restrict__ db) {
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += 256) s += dY[(size_t)c * P + p];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) db[c] = (float)(sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
+__global__ void k_relu_bwd(const float* __restrict__ Y, float* __restrict__ dY, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(Y[i] > 0.0f)) dY[i] = 0.0f;
+}
+
+__global__ void k_add(float* __restrict__ y, const float* __restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += x[i];
+}
+
+// coarse index (c, z, y, x) over [c][D/2][H/2][W/2]
+__global__ void k_pool(const float* __restrict__ X, int c, int D, int H, int W, float* __restrict__ Y) {
+    const int Dc = D / 2, Hc = H / 2, Wc = W / 2;
+    const int64_t total = (int64_t)c * Dc * Hc * Wc;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int x = i % Wc, y = (i / Wc) % Hc, z = (i / ((int64_t)Wc * Hc)) % Dc;
+    const int64_t ch = i / ((int64_t)Wc * Hc * Dc);
+    const float* b = X + (size_t)ch * D * H * W;
+    float s = 0.0f;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) s += b[((size_t)(2 * z + dz) * H + 2 * y + dy) * W + 2 * x + dx];
+    Y[i] = 0.125f * s;
+}
+
+// fine index over [c][D][H][W]
+__global__ void k_pool_bwd(const float* __restrict__ dY, int c, int D, int H, int W, float* __restrict__ dX,
+                           int accumulate) {
+    const int64_t total = (int64_t)c * D * H * W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int x = i % W, y = (i / W) % H, z = (i / ((int64_t)W * H)) % D;
+    const int64_t ch = i / ((int64_t)W * H * D);
+    const float v = 0.125f * dY[(((size_t)ch * (D / 2) + z / 2) * (H / 2) + y / 2) * (W / 2) + x / 2];
+    dX[i] = accumulate ? dX[i] + v : v;
+}
+
+// fine index over [c][2D][2H][2W], X coarse [c][D][H][W]
+__global__ void k_up(const float* __restrict__ X, int c, int D, int H, int W, float* __restrict__ Y) {
+    const int64_t total = (int64_t)c * 8 * D * H * W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int Wf = 2 * W, Hf = 2 * H, Df = 2 * D;
+    const int x = i % Wf, y = (i / Wf) % Hf, z = (i / ((int64_t)Wf * Hf)) % Df;
+    const int64_t ch = i / ((int64_t)Wf * Hf * Df);
+    Y[i] = X[(((size_t)ch * D + z / 2) * H + y / 2) * W + x / 2];
+}
+
+// coarse index over [c][D][H][W], dY fine
+__global__ void k_up_bwd(const float* __restrict__ dY, int c, int D, int H, int W, float* __restrict__ dX) {
+    const int64_t total = (int64_t)c * D * H * W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int x = i % W, y = (i / W) % H, z = (i / ((int64_t)W * H)) % D;
+    const int64_t ch = i / ((int64_t)W * H * D);
+    const int Wf = 2 * W, Hf = 2 * H, Df = 2 * D;
+    const float* b = dY + (size_t)ch * Df * Hf * Wf;
+    float s = 0.0f;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) s += b[((size_t)(2 * z + dz) * Hf + 2 * y + dy) * Wf + 2 * x + dx];
+    dX[i] = s;
+}
+
+__global__ void __launch_bounds__(256)
+    k_mse_partial(const float* __restrict__ Y, const float* __restrict__ T, const float* __restrict__ mask, int c,
+                  int64_t P, double* __restrict__ part) {
+    double s = 0.0, m = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < P; p += (int64_t)gridDim.x * 256) {
+        const float mk = mask[p];
+        m += mk;
+        for (int ch = 0; ch < c; ++ch) {
+            const double d = (double)Y[(size_t)ch * P + p] - (double)T[(size_t)ch * P + p];
+            s += mk * d * d;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        m += __shfl_xor(m, o, 64);
+    }
+    __shared__ double sh[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = s;
+        sh[1][threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+        part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    }
+}
+
+__global__ void k_mse_final(const double* __restrict__ part, int nblk, int c, double* __restrict__ loss,
+                            double* __restrict__ msum) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0, m = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        s += part[2 * b];
+        m += part[2 * b + 1];
+    }
+    *msum = m;
+    *loss = m > 0.0 ? s / (c * m) : 0.0;
+}
+
+__global__ void k_mse_grad(const float* __restrict__ Y, const float* __restrict__ T, const float* __restrict__ mask,
+                           int c, int64_t P, const double* __restrict__ msum, float* __restrict__ dY) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)c * P) return;
+    const int64_t p = i % P;
+    const double m = *msum;
+    dY[i] = m > 0.0 ? (float)(2.0 * mask[p] * ((double)Y[i] - (double)T[i]) / (c * m)) : 0.0f;
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+inline int grid1(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
+inline int ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_HIP; }
+
+int wgrad_chunks(int64_t P) { return P >= 65536 ? 64 : (P >= 4096 ? 8 : 1); }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_nn_packed_words(int c_out, int c_in) {
+    // enough for either precision and either orientation
+    const int cmax = c_out > c_in ? c_out : c_in;
+    const size_t a = (size_t)27 * cin_pad_of(cmax, LBM_NN_BF16) * cout_pad_of(cmax);
+    return a;  // fp32: one word per entry; bf16: half a word per entry
+}
+
+int lbm_nn_pack(const float* W, int c_out, int c_in, int transpose, int prec, uint32_t* packed, void* stream) {
+    if (!W || !packed || c_out < 1 || c_in < 1 || (prec != LBM_NN_BF16 && prec != LBM_NN_FP32)) return LBM_ERR_ARG;
+    const int lo = transpose ? c_in : c_out, li = transpose ? c_out : c_in;
+    const int total = 27 * cin_pad_of(li, prec) * cout_pad_of(lo);
+    hipLaunchKernelGGL(k_pack, dim3(grid1(total)), dim3(256), 0, (hipStream_t)stream, W, c_out, c_in, transpose,
+                       prec, packed);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* bias, const float* skip, float* Y,
+                int c_out, int D, int H, int W, int relu, int prec, void* stream) {
+    if (!X || !packed || !Y || c_in < 1 || c_out < 1 || D < 1 || H < 1 || W < 1) return LBM_ERR_ARG;
+    const int64_t P = (int64_t)D * H * W;
+    if (P * (c_in > c_out ? c_in : c_out) >= (1LL << 31)) return LBM_ERR_ARG;
+    dim3 grid((unsigned)((P + 127) / 128), (unsigned)((c_out + 31) / 32));
+    if (prec == LBM_NN_BF16)
+        hipLaunchKernelGGL(k_conv<LBM_NN_BF16>, grid, dim3(256), 0, (hipStream_t)stream, X, c_in, packed, bias,
+                           skip, Y, c_out, D, H, W, relu);
+    else if (prec == LBM_NN_FP32)
+        hipLaunchKernelGGL(k_conv<LBM_NN_FP32>, grid, dim3(256), 0, (hipStream_t)stream, X, c_in, packed, bias,
+                           skip, Y, c_out, D, H, W, relu);
+    else
+        return LBM_ERR_ARG;
+    return ok(hipGetLastError());
+}
+
+size_t lbm_nn_wgrad_partial_words(int c_out, int c_in, int D, int H, int W) {
+    const int64_t P = (int64_t)D * H * W;
+    return (size_t)wgrad_chunks(P) * c_out * c_in * 27;
+}
+
+int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, int H, int W, float* dW,
+                 float* partial, int prec, void* stream) {
+    if (!X || !dY || !dW || !partial || c_in < 1 || c_out < 1) return LBM_ERR_ARG;
+    const int64_t P = (int64_t)D * H * W;
+    const int nch = wgrad_chunks(P);
+    const int KS = prec == LBM_NN_BF16 ? 8 : 2;
+    int chunk = (int)((P + nch - 1) / nch);
+    chunk = (chunk + KS - 1) / KS * KS;
+    dim3 grid((unsigned)((c_out + 31) / 32), (unsigned)((c_in * 27 + 31) / 32), (unsigned)nch);
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == LBM_NN_BF16)
+        hipLaunchKernelGGL(k_wgrad<LBM_NN_BF16>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk, partial);
+    else if (prec == LBM_NN_FP32)
+        hipLaunchKernelGGL(k_wgrad<LBM_NN_FP32>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk, partial);
+    else
+        return LBM_ERR_ARG;
+    const int64_t n = (int64_t)c_out * c_in * 27;
+    hipLaunchKernelGGL(k_chunk_sum, dim3(grid1(n)), dim3(256), 0, st, partial, nch, n, dW);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_bias_grad(const float* dY, int c, int64_t P, float* db, void* stream) {
+    if (!dY || !db || c < 1) return LBM_ERR_ARG;
+    hipLaunchKernelGGL(k_bias_grad, dim3(c), dim3(256), 0, (hipStream_t)stream, dY, P, db);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_relu_bwd(const float* Y, float* dY, int64_t n, void* stream) {
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, Y, dY, n);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_add(float* y, const float* x, int64_t n, void* stream) {
+    hipLaunchKernelGGL(k_add, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, y, x, n);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_pool(const float* X, int c, int D, int H, int W, float* Y, void* stream) {
+    if ((D | H | W) & 1) return LBM_ERR_ARG;
+    const int64_t n = (int64_t)c * (D / 2) * (H / 2) * (W / 2);
+    hipLaunchKernelGGL(k_pool, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, X, c, D, H, W, Y);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_pool_bwd(const float* dY, int c, int D, int H, int W, float* dX, int accumulate, void* stream) {
+    if ((D | H | W) & 1) return LBM_ERR_ARG;
+    const int64_t n = (int64_t)c * D * H * W;
+    hipLaunchKernelGGL(k_pool_bwd, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, dY, c, D, H, W, dX, accumulate);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_up(const float* X, int c, int D, int H, int W, float* Y, void* stream) {
+    const int64_t n = (int64_t)c * 8 * D * H * W;
+    hipLaunchKernelGGL(k_up, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, X, c, D, H, W, Y);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_up_bwd(const float* dY, int c, int D, int H, int W, float* dX, void* stream) {
+    const int64_t n = (int64_t)c * D * H * W;
+    hipLaunchKernelGGL(k_up_bwd, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, dY, c, D, H, W, dX);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_mse(const float* Y, const float* T, const float* mask, int c, int64_t P, double* loss, float* dY,
+               void* stream) {
+    if (!Y || !T || !mask || !loss || c < 1 || P < 1) return LBM_ERR_ARG;
+    // loss[0] = L, loss[1..] scratch: caller provides 2 + 2*256 doubles
+    hipStream_t st = (hipStream_t)stream;
+    const int nblk = 256;
+    hipLaunchKernelGGL(k_mse_partial, dim3(nblk), dim3(256), 0, st, Y, T, mask, c, P, loss + 2);
+    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, st, loss + 2, nblk, c, loss, loss + 1);
+    if (dY)
+        hipLaunchKernelGGL(k_mse_grad, dim3(grid1((int64_t)c * P)), dim3(256), 0, st, Y, T, mask, c, P, loss + 1, dY);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                float eps, int t, void* stream) {
+    if (!p || !g || !m || !v || t < 1) return LBM_ERR_ARG;
+    const float c1 = 1.0f - powf(beta1, (float)t), c2 = 1.0f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n, lr, beta1, beta2,
+                       eps, c1, c2);
+    return ok(hipGetLastError());
+}
+
+}  // extern "C"

@@ -13,6 +13,7 @@ from paper_2506_17713_amd import inputs, lbm
 
 ROOT = Path(__file__).resolve().parents[1]
 HEADER = ROOT / "include" / "lbm.h"
+HEADERS = [ROOT / "include" / "lbm.h", ROOT / "include" / "lbm_nn.h"]
 
 
 @pytest.fixture(scope="module")
@@ -23,10 +24,12 @@ def lib():
     return lbm.load()
 
 
-def declared_functions():
-    text = HEADER.read_text()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+def declared_functions(headers=None):
+    names = set()
+    for hd in headers or HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", hd.read_text(), flags=re.S)
+        names |= set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -42,7 +45,9 @@ def test_library_exports_every_declared_symbol(lib):
     for n in declared_functions():
         assert n in exported, n
         assert hasattr(lib, n)
-    assert set(lbm.EXPORTS) == set(declared_functions())
+    from paper_2506_17713_amd import nn
+    assert set(lbm.EXPORTS) == set(declared_functions([HEADER]))
+    assert set(nn.EXPORTS) == set(declared_functions([HEADERS[1]]))
 
 
 def test_struct_layout_matches_header(tmp_path):

@@ -1,0 +1,201 @@
+"""Surrogate kernels (through the C-ABI) against the FP64 numpy oracle
+(oracle/nn_ref.py): convolution forward, data and weight gradients on the MFMA
+cores in FP32 (<= 1e-5) and BF16 (<= 2e-2), pooling, upsampling, masked MSE,
+Adam, and the whole network's weight gradients against finite differences of
+an oracle-built forward pass."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_2506_17713_amd import nn
+
+    return nn
+
+
+SHAPES = [(1, 16, (8, 6, 10)), (16, 3, (8, 8, 8)), (35, 40, (6, 10, 12)), (64, 64, (4, 4, 4))]
+
+
+@pytest.mark.parametrize("cin,cout,dhw", SHAPES)
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 2e-2)])
+def test_conv_forward(T, ops, cin, cout, dhw, prec, tol):
+    from oracle import nn_ref
+
+    rng = np.random.default_rng(cin * 100 + cout)
+    X = rng.standard_normal((cin,) + dhw)
+    W = rng.standard_normal((cout, cin, 27)) / np.sqrt(cin * 27)
+    b = rng.standard_normal(cout)
+    S = rng.standard_normal((cout,) + dhw)
+    d = lambda a: T.tensor(a, dtype=T.float32, device="cuda").contiguous()
+    pk = ops.pack(d(W), False, prec)
+    Y = ops.conv(d(X), pk, cout, bias=d(b), skip=d(S), relu=True, prec=prec).cpu().double().numpy()
+    ref = nn_ref.conv(X, W, b, relu=True, skip=S)
+    assert rel(Y, ref) < tol
+    Y2 = ops.conv(d(X), pk, cout, prec=prec).cpu().double().numpy()
+    assert rel(Y2, nn_ref.conv(X, W)) < tol
+
+
+@pytest.mark.parametrize("cin,cout,dhw", SHAPES)
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 2e-2)])
+def test_conv_data_gradient(T, ops, cin, cout, dhw, prec, tol):
+    from oracle import nn_ref
+
+    rng = np.random.default_rng(7 + cin)
+    W = rng.standard_normal((cout, cin, 27))
+    dY = rng.standard_normal((cout,) + dhw)
+    d = lambda a: T.tensor(a, dtype=T.float32, device="cuda").contiguous()
+    pkT = ops.pack(d(W), True, prec)
+    dX = ops.conv(d(dY), pkT, cin, prec=prec).cpu().double().numpy()
+    assert rel(dX, nn_ref.dgrad(W, dY)) < tol
+
+
+@pytest.mark.parametrize("cin,cout,dhw", SHAPES + [(16, 32, (32, 32, 32))])
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 2e-2)])
+def test_conv_weight_gradient(T, ops, cin, cout, dhw, prec, tol):
+    from oracle import nn_ref
+
+    rng = np.random.default_rng(3 + cout)
+    X = rng.standard_normal((cin,) + dhw)
+    dY = rng.standard_normal((cout,) + dhw)
+    d = lambda a: T.tensor(a, dtype=T.float32, device="cuda").contiguous()
+    dW = ops.wgrad(d(X), d(dY), prec).cpu().double().numpy()
+    assert rel(dW, nn_ref.wgrad(X, dY)) < tol
+    db = ops.bias_grad(d(dY)).cpu().double().numpy()
+    assert rel(db, dY.sum(axis=(1, 2, 3))) < 1e-5
+
+
+def test_pool_up_relu_add(T, ops):
+    from oracle import nn_ref
+
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((5, 8, 6, 10))
+    d = lambda a: T.tensor(a, dtype=T.float32, device="cuda").contiguous()
+    P = ops.pool(d(X)).cpu().double().numpy()
+    assert rel(P, nn_ref.pool(X)) < 1e-6
+    U = ops.up(d(P)).cpu().double().numpy()
+    assert rel(U, nn_ref.up(P)) < 1e-6
+    # adjoints: <pool(X), G> = <X, pool_bwd(G)>, <up(Y), G> = <Y, up_bwd(G)>
+    G = rng.standard_normal((5, 4, 3, 5))
+    dX = T.empty((5, 8, 6, 10), dtype=T.float32, device="cuda")
+    ops.pool_bwd(d(G), dX, accumulate=False)
+    assert abs((nn_ref.pool(X) * G).sum() - (X * dX.cpu().double().numpy()).sum()) < 1e-4
+    G2 = rng.standard_normal((5, 8, 6, 10))
+    uy = ops.up_bwd(d(G2)).cpu().double().numpy()
+    assert abs((nn_ref.up(P) * G2).sum() - (P * uy).sum()) < 1e-4
+    Y = d(X)
+    dY = d(np.ones_like(X))
+    ops.relu_bwd(Y, dY)
+    assert np.array_equal(dY.cpu().numpy(), (X > 0).astype(np.float32))
+    a = d(X)
+    ops.add_(a, d(2 * X))
+    assert rel(a.cpu().double().numpy(), 3 * X) < 1e-6
+
+
+def test_mse_and_adam(T, ops):
+    from oracle import nn_ref
+
+    rng = np.random.default_rng(2)
+    Y = rng.standard_normal((3, 6, 4, 8))
+    Tt = rng.standard_normal((3, 6, 4, 8))
+    mask = (rng.uniform(size=(6, 4, 8)) > 0.4).astype(np.float64)
+    d = lambda a: T.tensor(a, dtype=T.float32, device="cuda").contiguous()
+    L, dY = ops.mse(d(Y), d(Tt), d(mask))
+    Lr, dYr = nn_ref.mse(Y.astype(np.float32).astype(np.float64), Tt.astype(np.float32).astype(np.float64), mask)
+    assert float(L) == pytest.approx(Lr, rel=1e-12)
+    assert rel(dY.cpu().double().numpy(), dYr) < 1e-6
+    p = rng.standard_normal(1000)
+    g = rng.standard_normal(1000)
+    m = np.zeros(1000)
+    v = np.zeros(1000)
+    pt, gt, mt, vt = d(p), d(g), d(m), d(v)
+    for t in range(1, 4):
+        ops.adam_(pt, gt, mt, vt, t, 1e-2)
+        p, m, v = nn_ref.adam(p, g, m, v, t, 1e-2)
+    assert rel(pt.cpu().double().numpy(), p) < 1e-5
+
+
+def _oracle_forward(model, X):
+    """The surrogate's wiring composed from oracle operations (FP64)."""
+    from oracle import nn_ref
+
+    W = {n: model.W[n].cpu().double().numpy() for n in model.W}
+    b = {n: model.b[n].cpu().double().numpy() for n in model.b}
+    c = lambda n, x, r=True: nn_ref.conv(x, W[n], b[n], relu=r)
+    s0 = c("enc0b", c("enc0a", X))
+    s1 = c("enc1b", c("enc1a", nn_ref.pool(s0)))
+    s2 = c("enc2b", c("enc2a", nn_ref.pool(s1)))
+    a = c("botb", c("bota", nn_ref.pool(s2)))
+    a = c("dec2b", c("dec2a", nn_ref.up(a)) + s2)
+    a = c("dec1b", c("dec1a", nn_ref.up(a)) + s1)
+    a = c("dec0b", c("dec0a", nn_ref.up(a)) + s0)
+    return c("head", a, False)
+
+
+def test_network_gradient_against_oracle_finite_differences(T, ops):
+    from oracle import nn_ref
+    from paper_2506_17713_amd.surrogate import Surrogate
+
+    rng = np.random.default_rng(5)
+    model = Surrogate(prec=ops.FP32, seed=3)
+    # larger biases so that few ReLUs sit at their kink
+    for n in model.b:
+        model.b[n].copy_(T.tensor(rng.uniform(0.05, 0.2, model.b[n].shape), dtype=T.float32))
+    model.repack()
+    D = 16
+    mask = (rng.uniform(size=(1, D, D, D)) > 0.4).astype(np.float64)
+    target = rng.standard_normal((3, D, D, D))
+    d = lambda a: T.tensor(a, dtype=T.float32, device="cuda").contiguous()
+    tape = []
+    out = model.forward(d(mask), tape)
+    ref_out = _oracle_forward(model, mask)
+    assert rel(out.cpu().double().numpy(), ref_out) < 1e-4
+    L, dout = ops.mse(out, d(target), d(mask[0]))
+    grads = model.backward(tape, dout)
+
+    def loss_of(name, idx, h):
+        W0 = model.W[name].clone()
+        Wn = W0.cpu().double().numpy().copy()
+        Wn[idx] += h
+        model.W[name].copy_(T.tensor(Wn, dtype=T.float32))
+        o = _oracle_forward(model, mask)
+        model.W[name].copy_(W0)
+        return nn_ref.mse(o, target, mask[0])[0]
+
+    checks = [("enc0a", (3, 0, 13)), ("enc1b", (5, 7, 2)), ("botb", (100, 64, 26)), ("dec1a", (9, 40, 4)),
+              ("head", (1, 11, 20)), ("dec0b", (2, 3, 0))]
+    errs = []
+    for name, idx in checks:
+        # FD of the oracle forward in FP64 at the FP32-rounded weights
+        h = 1e-4 * max(1.0, abs(float(model.W[name][idx])))
+        fd = (loss_of(name, idx, h) - loss_of(name, idx, -h)) / (2 * h)
+        g = float(grads[name][0][idx])
+        errs.append(abs(g - fd) / max(abs(fd), 1e-6))
+    assert max(errs) < 2e-3, errs
+
+
+def test_training_reduces_the_loss(T, ops):
+    from paper_2506_17713_amd import inputs
+    from paper_2506_17713_amd.surrogate import Surrogate, train
+
+    rng = np.random.default_rng(0)
+    D = 32
+    solid = inputs.sphere_pack((D, D, D), (3.0, 6.0), 0.45, seed=4)
+    mask = T.tensor((solid == 0).astype(np.float32)[None], device="cuda")
+    target = rng.standard_normal((3, D, D, D)) * (solid == 0)[None] + 0.5
+    model = Surrogate(prec=ops.BF16, seed=1)
+    hist = train(model, [mask], [target], epochs=30, lr=3e-3)
+    assert hist[-1] < 0.8 * hist[0]
