@@ -56,6 +56,23 @@ def algorithmic_bytes(w, solid) -> float:
     return float(n_fluid * per_fluid + w.N)
 
 
+def measured_traffic(w) -> float | None:
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
+    measurement (profiles/k_step_traffic.json), scaled by the same counters on
+    a 1 GiB copy; None if the kernel sources changed since, or for another
+    workload."""
+    import hashlib
+
+    path = ROOT / "profiles" / "k_step_traffic.json"
+    if not path.exists() or w.storage != "F32" or w.collision != "MRT" or w.shape != (256, 256, 256):
+        return None
+    rec = json.loads(path.read_text())
+    h = hashlib.sha256()
+    for p in ("paper_2506_17713_amd/csrc/lbm_device.hpp", "paper_2506_17713_amd/csrc/lbm_api.hip"):
+        h.update((ROOT / p).read_bytes())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["kernel_source_sha256"] else None
+
+
 def cpu_baseline(budget_s: float) -> dict:
     """FP64 oracle on a 64^3 version of the same workload, as many steps as fit
     the time budget (first step excluded)."""
@@ -115,6 +132,7 @@ def main():
     achieved = b_alg / (ms_step * 1e-3) / 1e9
     print(f"# {args.steps} steps: {ms:.2f} ms (events), wall {wall:.3f} s, mass {stats['mass'][0]:.6e}, "
           f"nonfinite {stats['nonfinite']}", file=sys.stderr, flush=True)
+    traffic = measured_traffic(w)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)
@@ -136,7 +154,7 @@ def main():
                                f"r=30 wall z=0 phi=1.1", "nodes": w.N, "components": w.nc,
                    "storage": w.storage, "fluid_nodes": int((solid == 0).sum())},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": b_alg, "kernel": "k_step (fused step)"},
         "cpu_baseline": cpu,
     }

@@ -166,11 +166,14 @@ class Surrogate:
 NU = (1.0 - 0.5) / 3.0  # BGK tau = 1
 
 
-def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, tol=1e-6, check=100, max_steps=100000, device="cuda"):
+def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, tol=1e-6, check=100, max_steps=100000, device="cuda",
+                 storage="F64"):
     """Run single-phase flow (BGK tau = 1, rho = 1, body acceleration along x)
     until the residual sum|u_x(t) - u_x(t-100)| / sum|u_x| < tol.
-    Returns dict(u [3, N] torch float32, steps, seconds, k, residual)."""
-    w, solid, rho = inputs.single_phase_pack(shape=solid.shape, solid=solid, accel=accel)
+    FP64 populations by default: with u ~ 1e-4 the FP32 rounding noise of the
+    velocity alone keeps this residual near 3e-5.
+    Returns dict(u [3, N] torch tensor, steps, seconds, k, residual)."""
+    w, solid, rho = inputs.single_phase_pack(shape=solid.shape, solid=solid, accel=accel, storage=storage)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sol = lbm.Solver(w, solid, rho, u0=u0, device=device)
