@@ -116,7 +116,9 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
  *   p          parameters, copied.
  *   mask       host uint8[N], 1 = solid node (walls, grains), 0 = fluid.
  *   rho0       host double[n_comp][N], initial density per component.
- *   u0         host double[3][N] initial velocity (x, y, z), or NULL for rest.
+ *   u0         host double[3][N] initial equilibrium velocity j/rho (x, y, z),
+ *              or NULL for rest.  The velocity of Eq. 6 reported by
+ *              lbm_moments adds F/(2 rho) to it.
  *   wet        host double[n_comp][N] per-node phi / drho (used at solid
  *              nodes), or NULL to use p->wet uniformly.
  *   workspace  device buffer of ws_bytes >= lbm_workspace_size(p); owned by

@@ -13,9 +13,13 @@
 using namespace lbm;
 using namespace lbmi;
 
-// Build-time tile configuration of the 3-D 32-bit kernels: tile height along y
-// (the tile is 32 x LBM_TILE_B nodes) and whether own-node populations are
-// carried in registers from the pull to the collision.
+// Build-time tile configuration of the 3-D 32-bit kernels: the tile is
+// LBM_TILE_A x LBM_TILE_B nodes in (x, y), and LBM_CARRY selects whether
+// own-node populations are carried in registers from the pull to the
+// collision.
+#ifndef LBM_TILE_A
+#define LBM_TILE_A 32
+#endif
 #ifndef LBM_TILE_B
 #define LBM_TILE_B 8
 #endif
@@ -151,7 +155,7 @@ void fill_args(lbm_handle* h, StepArgs<R>& a, const Buffers* bufs) {
 
 template <int LAT, int NC, int ST, int COLL, bool MOM>
 hipError_t launch_step(lbm_handle* h, StepArgs<typename Store<ST>::R>& a) {
-    constexpr int TA = LAT == LAT_D2Q9 ? 64 : 32;
+    constexpr int TA = LAT == LAT_D2Q9 ? 64 : LBM_TILE_A;
     constexpr int TB = LAT == LAT_D2Q9 ? 1 : (ST == ST_F64 ? 4 : LBM_TILE_B);
     a.tiles_a = (h->NA + TA - 1) / TA;
     a.tiles_b = (h->NB + TB - 1) / TB;

@@ -129,6 +129,153 @@ __host__ __device__ constexpr double mrt_norm(int m) {
     return s;
 }
 
+// Row m is even (same coefficient on e_i and -e_i) or odd (opposite sign).
+template <int LAT>
+__host__ __device__ constexpr bool mrt_even(int m) {
+    for (int i = 1; i < Lat<LAT>::Q; ++i)
+        if (mrt_coef<LAT>(m, i) != mrt_coef<LAT>(m, opp(i))) return false;
+    return true;
+}
+// Row m is a momentum component (e_x, e_y or e_z).
+template <int LAT>
+__host__ __device__ constexpr bool mrt_momentum(int m) {
+    using L = Lat<LAT>;
+    bool isx = true, isy = true, isz = LAT == LAT_D3Q19;
+    for (int i = 0; i < L::Q; ++i) {
+        isx = isx && mrt_coef<LAT>(m, i) == L::ex[i];
+        isy = isy && mrt_coef<LAT>(m, i) == L::ey[i];
+        isz = isz && mrt_coef<LAT>(m, i) == L::ez[i];
+    }
+    return isx || isy || isz;
+}
+
+// D3Q19 MRT in pair form.  Pair p holds directions 2p+1 and 2p+2 (opposite);
+// dp = d_i + d_{i+1}, dm = d_i - d_{i+1} of d = f - f^eq, d0 the rest entry.
+// Applies m = diag(s) M d (rows of mrt_coef, s already divided by |row|^2)
+// and returns M^T m as E (even rows) and O (odd rows): (M^T m)_{2p+1} = E_p +
+// O_p, (M^T m)_{2p+2} = E_p - O_p.  Rows 0 (density) and, unless JROWS, 3, 5,
+// 7 (momentum) are left out.  The row sums are factored over the shared
+// sub-sums of each |e|^2 class: the products are those of mrt_coef, in fewer
+// operations (pinned to the full matrix product by the parity tests).
+template <class R, bool JROWS>
+__host__ __device__ __forceinline__ void mrt_pairs_d3q19(const R (&dp)[9], const R (&dm)[9], R d0,
+                                                         const R (&s)[19], R (&E)[9], R (&O)[9]) {
+    // even rows: 1, 2 (energy), 9-12 (normal stress), 13-15 (shear)
+    const R A = dp[0] + dp[1] + dp[2];
+    const R C = dp[3] + dp[4], D = dp[5] + dp[6], G = dp[7] + dp[8];
+    const R B = C + D + G;
+    const R m1 = ((R)-30 * d0 - (R)11 * A + (R)8 * B) * s[1];
+    const R m2 = ((R)12 * d0 - (R)4 * A + B) * s[2];
+    const R Y = (R)2 * dp[0] - (dp[1] + dp[2]);
+    const R X = (C + D) - (R)2 * G;
+    const R m9 = (Y + X) * s[9];
+    const R m10 = (X - (R)2 * Y) * s[10];
+    const R Z = dp[1] - dp[2], W = C - D;
+    const R m11 = (Z + W) * s[11];
+    const R m12 = (W - (R)2 * Z) * s[12];
+    const R m13 = (dp[3] - dp[4]) * s[13];
+    const R m14 = (dp[7] - dp[8]) * s[14];
+    const R m15 = (dp[5] - dp[6]) * s[15];
+    // odd rows: 3, 5, 7 (momentum), 4, 6, 8 (energy flux), 16-18
+    const R Px = dm[3] + dm[4], Qx = dm[5] + dm[6];
+    const R Ry = dm[3] - dm[4], Sy = dm[7] + dm[8];
+    const R Tz = dm[5] - dm[6], Uz = dm[7] - dm[8];
+    const R m4 = ((R)-4 * dm[0] + Px + Qx) * s[4];
+    const R m6 = ((R)-4 * dm[1] + Ry + Sy) * s[6];
+    const R m8 = ((R)-4 * dm[2] + Tz + Uz) * s[8];
+    const R m16 = (Px - Qx) * s[16];
+    const R m17 = (Sy - Ry) * s[17];
+    const R m18 = (Tz - Uz) * s[18];
+    R m3 = 0, m5 = 0, m7 = 0;
+    if constexpr (JROWS) {
+        m3 = (dm[0] + Px + Qx) * s[3];
+        m5 = (dm[1] + Ry + Sy) * s[5];
+        m7 = (dm[2] + Tz + Uz) * s[7];
+    }
+    // back: even part
+    const R Ea = (R)-11 * m1 - (R)4 * m2, Ed = (R)8 * m1 + m2;
+    const R K = m9 + m10, L2 = m11 + m12;
+    E[0] = Ea + (R)2 * m9 - (R)4 * m10;
+    const R v1 = (R)2 * m10 - m9, h1 = m11 - (R)2 * m12;
+    E[1] = Ea + v1 + h1;
+    E[2] = Ea + v1 - h1;
+    const R b34 = Ed + K + L2, b56 = Ed + K - L2, b78 = Ed - (R)2 * K;
+    E[3] = b34 + m13;
+    E[4] = b34 - m13;
+    E[5] = b56 + m15;
+    E[6] = b56 - m15;
+    E[7] = b78 + m14;
+    E[8] = b78 - m14;
+    // back: odd part
+    const R X4 = m3 + m4, Y6 = m5 + m6, Z8 = m7 + m8;
+    O[0] = m3 - (R)4 * m4;
+    O[1] = m5 - (R)4 * m6;
+    O[2] = m7 - (R)4 * m8;
+    O[3] = X4 + Y6 + (m16 - m17);
+    O[4] = X4 - Y6 + (m16 + m17);
+    O[5] = X4 + Z8 + (m18 - m16);
+    O[6] = X4 - Z8 - (m16 + m18);
+    O[7] = Y6 + Z8 + (m17 - m18);
+    O[8] = Y6 - Z8 + (m17 + m18);
+}
+
+// e.(x, y, z) for a compile-time e with components in {-1, 0, 1}, written
+// without multiplications by the constants: IEEE arithmetic does not fold
+// 0 * x or x + 0, so the plain dot product would spend instructions on them.
+template <int CX, int CY, int CZ, class R>
+__host__ __device__ __forceinline__ R dot_e(R x, R y, R z) {
+    if constexpr (CX != 0) {
+        R s = CX > 0 ? x : -x;
+        if constexpr (CY != 0) s = CY > 0 ? s + y : s - y;
+        if constexpr (CZ != 0) s = CZ > 0 ? s + z : s - z;
+        return s;
+    } else if constexpr (CY != 0) {
+        R s = CY > 0 ? y : -y;
+        if constexpr (CZ != 0) s = CZ > 0 ? s + z : s - z;
+        return s;
+    } else if constexpr (CZ != 0) {
+        return CZ > 0 ? z : -z;
+    } else {
+        return (R)0;
+    }
+}
+
+// Signed sums over opposite pairs: acc[d] = sum_p e_d(2p+1) v[p] over the
+// pairs with e_d != 0 (and, with CLS >= 0, only pairs of weight class CLS:
+// 0 = the class of direction 1, 1 = the others).  The first contributing
+// term initialises the sum, so no 0 + x is issued.
+template <int LAT>
+__host__ __device__ constexpr int pair_e(int p, int d) {
+    using L = Lat<LAT>;
+    return d == 0 ? L::ex[2 * p + 1] : (d == 1 ? L::ey[2 * p + 1] : L::ez[2 * p + 1]);
+}
+template <int LAT>
+__host__ __device__ constexpr bool pair_in(int p, int cls) {
+    return cls < 0 || ((Lat<LAT>::w(2 * p + 1) == Lat<LAT>::w(1)) == (cls == 0));
+}
+template <int LAT>
+__host__ __device__ constexpr int first_pair(int d, int cls) {
+    for (int p = 0; p < (Lat<LAT>::Q - 1) / 2; ++p)
+        if (pair_in<LAT>(p, cls) && pair_e<LAT>(p, d) != 0) return p;
+    return -1;
+}
+template <int LAT, int CLS, class R, int NP>
+__device__ __forceinline__ void pair_sums(const R (&v)[NP], R (&acc)[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc[d] = (R)0;
+    sfor<3>([&](auto D) {
+        constexpr int d = decltype(D)::value;
+        sfor<NP>([&](auto PI) {
+            constexpr int p = decltype(PI)::value;
+            constexpr int e = pair_e<LAT>(p, d);
+            if constexpr (e != 0 && pair_in<LAT>(p, CLS)) {
+                if constexpr (p == first_pair<LAT>(d, CLS)) acc[d] = e > 0 ? v[p] : -v[p];
+                else acc[d] = e > 0 ? acc[d] + v[p] : acc[d] - v[p];
+            }
+        });
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Population storage formats.
 // ---------------------------------------------------------------------------
@@ -205,6 +352,14 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
 
 // ---------------------------------------------------------------------------
 // Pull of all directions of one node (all components).
+//
+// The plane index c is the same for every lane of a wavefront (a workgroup
+// works on one plane at a time), so the address of a population splits into
+// a wavefront-uniform 64-bit base (array, component, direction, source plane:
+// scalar registers and scalar ALU) and a 32-bit per-lane offset inside the
+// plane.  The in-plane offset of the source x - e_i depends only on
+// (e_a, e_b), so nine adds cover all directions and each load costs one
+// vector instruction besides itself.
 // ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC>
 __device__ __forceinline__ void pull_node(const StepArgs<typename Store<ST>::R>& P, int n, int a,
@@ -215,14 +370,23 @@ __device__ __forceinline__ void pull_node(const StepArgs<typename Store<ST>::R>&
     using S = typename SS::S;
     using R = typename SS::R;
     constexpr int Q = L::Q;
+    (void)n;
     const int NA = P.NA, NB = P.NB, NCc = P.NC_;
-    const int plane = NA * NB;
-    // index deltas of the neighbour at -1, 0, +1 along each axis (periodic)
-    const int dA[3] = {a == 0 ? NA - 1 : -1, 0, a == NA - 1 ? 1 - NA : 1};
-    const int dB[3] = {b == 0 ? (NB - 1) * NA : -NA, 0, b == NB - 1 ? (1 - NB) * NA : NA};
-    const int dC[3] = {c == 0 ? (NCc - 1) * plane : -plane, 0, c == NCc - 1 ? (1 - NCc) * plane : plane};
-    const S* fin = reinterpret_cast<const S*>(P.fin);
-    const size_t N = (size_t)P.N;
+    const size_t plane = (size_t)NA * NB;
+    // the direction stride is made opaque here so that the per-direction
+    // bases are formed in the loop by the scalar unit instead of being kept
+    // live across it (which spills scalar registers)
+    size_t N = (size_t)P.N;
+    asm volatile("" : "+s"(N));
+    // source coordinate x - e for e = -1, 0, +1 (index e + 1), periodic
+    const uint32_t col[3] = {(uint32_t)(a == NA - 1 ? 0 : a + 1), (uint32_t)a, (uint32_t)(a == 0 ? NA - 1 : a - 1)};
+    const uint32_t row[3] = {(uint32_t)((b == NB - 1 ? 0 : b + 1) * NA), (uint32_t)(b * NA),
+                             (uint32_t)((b == 0 ? NB - 1 : b - 1) * NA)};
+    const size_t cs[3] = {(size_t)(c == NCc - 1 ? 0 : c + 1), (size_t)c, (size_t)(c == 0 ? NCc - 1 : c - 1)};
+    const char* fb = reinterpret_cast<const char*>(P.fin);
+    const char* rb = reinterpret_cast<const char*>(P.rin);
+    auto ld = [](const char* base, uint32_t off) { return *reinterpret_cast<const S*>(base + off); };
+    auto ldr = [](const char* base, uint32_t off) { return *reinterpret_cast<const float*>(base + off); };
     // streaming loads do not depend on the neighbour word, so they issue
     // together with it; a source that is solid holds no population and its
     // value is replaced by the bounced one below
@@ -230,23 +394,31 @@ __device__ __forceinline__ void pull_node(const StepArgs<typename Store<ST>::R>&
     float rs[NC][Q];
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        const int src = n + dA[1 - L::ea(i)] + dB[1 - L::eb(i)] + dC[1 - L::ec(i)];
+        uint32_t e = row[L::eb(i) + 1] + col[L::ea(i) + 1];
+        // keep the offset a 32-bit value computed here: hoisted out of the
+        // plane loop it would be widened to 64 bits and the loads would lose
+        // the scalar-base addressing form
+        asm volatile("" : "+v"(e));
+        const size_t pl = cs[L::ec(i) + 1] * plane;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            v[k][i] = fin[(size_t)(k * Q + i) * N + src];
-            if constexpr (SS::DEV) rs[k][i] = P.rin[(size_t)k * N + src];
+            v[k][i] = ld(fb + ((size_t)(k * Q + i) * N + pl) * sizeof(S), e * (uint32_t)sizeof(S));
+            if constexpr (SS::DEV) rs[k][i] = ldr(rb + ((size_t)k * N + pl) * 4, e * 4u);
         }
     });
     if (word & ~1u) {
         // halfway bounce-back: f_i(x) = f*_opp(i)(x) when x - e_i is solid
+        uint32_t e = row[1] + col[1];
+        asm volatile("" : "+v"(e));
+        const size_t pl = cs[1] * plane;
         sfor<Q - 1>([&](auto I) {
             constexpr int i = decltype(I)::value + 1;
             constexpr int o = opp(i);
             if ((word >> i) & 1u) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
-                    v[k][i] = fin[(size_t)(k * Q + o) * N + n];
-                    if constexpr (SS::DEV) rs[k][i] = P.rin[(size_t)k * N + n];
+                    v[k][i] = ld(fb + ((size_t)(k * Q + o) * N + pl) * sizeof(S), e * (uint32_t)sizeof(S));
+                    if constexpr (SS::DEV) rs[k][i] = ldr(rb + ((size_t)k * N + pl) * 4, e * 4u);
                 }
             }
         });
@@ -270,12 +442,21 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
     if (P.psi_cs[k]) {
         const R eta = P.eos_b[k] * rho * (R)0.25;
         const R om = (R)1 - eta;
-        const R p = rho * P.eos_RT[k] * ((R)1 + eta + eta * eta - eta * eta * eta) / (om * om * om) -
-                    P.eos_a[k] * rho * rho;
+        R p;
+        if constexpr (std::is_same<R, float>::value) {
+            // hardware reciprocal and square root (1 ulp each) in single precision
+            const float io = __builtin_amdgcn_rcpf(om);
+            p = rho * P.eos_RT[k] * ((R)1 + eta + eta * eta - eta * eta * eta) * (io * io * io) -
+                P.eos_a[k] * rho * rho;
+        } else {
+            p = rho * P.eos_RT[k] * ((R)1 + eta + eta * eta - eta * eta * eta) / (om * om * om) -
+                P.eos_a[k] * rho * rho;
+        }
         const R u = P.alpha[k] * p - rho * (R)(1.0 / 3.0);
         R arg = (R)2 * u * P.ginv[k];
         arg = arg > (R)0 ? arg : (R)0;
-        psi = sqrt(arg);
+        if constexpr (std::is_same<R, float>::value) psi = __builtin_amdgcn_sqrtf(arg);
+        else psi = sqrt(arg);
         U = u;
     } else {
         psi = rho;
@@ -502,59 +683,77 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
         // moments (Eq. 4); the momentum is summed over differences of opposite
         // populations, which are exact in floating point when the two are
         // within a factor of two of each other (Sterbenz)
+        constexpr int NP = (Q - 1) / 2;
         R rho[NC], j[NC][3];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            R r = f[k][0], jx = 0, jy = 0, jz = 0;
-            sfor<(Q - 1) / 2>([&](auto PI) {
-                constexpr int i = 2 * decltype(PI)::value + 1;  // e_{i+1} = -e_i
+            R r = f[k][0], dl[NP];
+            sfor<NP>([&](auto PI) {
+                constexpr int p = decltype(PI)::value;
+                constexpr int i = 2 * p + 1;  // e_{i+1} = -e_i
                 r += f[k][i] + f[k][i + 1];
-                const R d = f[k][i] - f[k][i + 1];
-                if constexpr (L::ex[i] != 0) jx += L::ex[i] > 0 ? d : -d;
-                if constexpr (L::ey[i] != 0) jy += L::ey[i] > 0 ? d : -d;
-                if constexpr (L::ez[i] != 0) jz += L::ez[i] > 0 ? d : -d;
+                dl[p] = f[k][i] - f[k][i + 1];
             });
             rho[k] = r;
-            j[k][0] = jx;
-            j[k][1] = jy;
-            j[k][2] = jz;
+            pair_sums<LAT, -1>(dl, j[k]);
         }
-        // interaction force (Eq. 13) with G_i = w_i / c_s^2
+        // interaction force (Eq. 13) with G_i = w_i / c_s^2.  The sums over
+        // directions are taken as differences across opposite neighbours,
+        // psi(x + e_i) - psi(x - e_i), gathered per weight class and scaled
+        // once per class: D^kk = sum_i G_i psi^kk(x + e_i) e_i.
         const int sc = (c - c0 + 3) % 3;
         const int pc = (lb + H1B) * PWA + la + 1;
-        R F[NC][3];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            // sum_i G_i psi(x + e_i) e_i taken as differences across opposite
-            // neighbours, psi(x + e_i) - psi(x - e_i)
-            R sx = 0, sy = 0, sz = 0, zx = 0, zy = 0, zz = 0;
-            sfor<(Q - 1) / 2>([&](auto PI) {
+        constexpr R G0 = (R)(3.0 * L::w(1));                // class of direction 1
+        constexpr R G1 = (R)(3.0 * L::w(Q - 1));            // the other class
+        auto gather = [&](const R(&ring)[3][NC][PP], int kk, R(&out)[3]) {
+            R dv[NP];
+            sfor<NP>([&](auto PI) {
                 constexpr int i = 2 * decltype(PI)::value + 1;
-                constexpr R G = (R)(3.0 * L::w(i));
                 const int slp = (c + L::ec(i) - c0 + 3) % 3;
                 const int slm = (c - L::ec(i) - c0 + 3) % 3;
                 const int offp = pc + L::eb(i) * PWA + L::ea(i);
                 const int offm = pc - L::eb(i) * PWA - L::ea(i);
-                R s = 0;
-#pragma unroll
-                for (int kk = 0; kk < NC; ++kk)
-                    s += P.g[k][kk] * (s_psi[slp][kk][offp] - s_psi[slm][kk][offm]);
-                s *= G;
-                if constexpr (L::ex[i] != 0) sx += L::ex[i] > 0 ? s : -s;
-                if constexpr (L::ey[i] != 0) sy += L::ey[i] > 0 ? s : -s;
-                if constexpr (L::ez[i] != 0) sz += L::ez[i] > 0 ? s : -s;
-                if (P.has_zc) {
-                    const R uu = G * (s_U[slp][k][offp] - s_U[slm][k][offm]);
-                    if constexpr (L::ex[i] != 0) zx += L::ex[i] > 0 ? uu : -uu;
-                    if constexpr (L::ey[i] != 0) zy += L::ey[i] > 0 ? uu : -uu;
-                    if constexpr (L::ez[i] != 0) zz += L::ez[i] > 0 ? uu : -uu;
-                }
+                dv[decltype(PI)::value] = ring[slp][kk][offp] - ring[slm][kk][offm];
             });
+            R s0[3], s1[3];
+            pair_sums<LAT, 0>(dv, s0);
+            pair_sums<LAT, 1>(dv, s1);
+            sfor<3>([&](auto D) {
+                constexpr int d = decltype(D)::value;
+                constexpr bool h0 = first_pair<LAT>(d, 0) >= 0, h1 = first_pair<LAT>(d, 1) >= 0;
+                if constexpr (h0 && h1) out[d] = G0 * s0[d] + G1 * s1[d];
+                else if constexpr (h0) out[d] = G0 * s0[d];
+                else if constexpr (h1) out[d] = G1 * s1[d];
+                else out[d] = (R)0;
+            });
+        };
+        R Dps[NC][3];
+#pragma unroll
+        for (int kk = 0; kk < NC; ++kk) gather(s_psi, kk, Dps[kk]);
+        R F[NC][3];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
             const R psik = s_psi[sc][k][pc];
-            const R Ak = P.A[k], Bk = (R)1 - P.A[k];
-            F[k][0] = -Ak * zx - Bk * psik * sx + rho[k] * P.body[0];
-            F[k][1] = -Ak * zy - Bk * psik * sy + rho[k] * P.body[1];
-            F[k][2] = -Ak * zz - Bk * psik * sz + rho[k] * P.body[2];
+            const R Bk = (R)1 - P.A[k];
+            R sv[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                R t = P.g[k][0] * Dps[0][d];
+#pragma unroll
+                for (int kk = 1; kk < NC; ++kk) t += P.g[k][kk] * Dps[kk][d];
+                sv[d] = t;
+            }
+            const R cpsi = -Bk * psik;
+            F[k][0] = cpsi * sv[0] + rho[k] * P.body[0];
+            F[k][1] = cpsi * sv[1] + rho[k] * P.body[1];
+            F[k][2] = cpsi * sv[2] + rho[k] * P.body[2];
+            if (P.has_zc) {
+                R zu[3];
+                gather(s_U, k, zu);
+                F[k][0] -= P.A[k] * zu[0];
+                F[k][1] -= P.A[k] * zu[1];
+                F[k][2] -= P.A[k] * zu[2];
+            }
         }
 
         if constexpr (MOM) {
@@ -613,51 +812,119 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
                 const R dx = F[k][0] * invr, dy = F[k][1] * invr, dz = F[k][2] * invr;
                 const R usq = (R)1.5 * (ux * ux + uy * uy + uz * uz);
                 const R dsq = (R)1.5 * ((R)2 * (ux * dx + uy * dy + uz * dz) + dx * dx + dy * dy + dz * dz);
-                R feq[Q], dF[Q];
-                sfor<Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    constexpr R ex = L::ex[i], ey = L::ey[i], ez = L::ez[i];
-                    const R wr = (R)L::w(i) * r;
-                    const R eu = ex * ux + ey * uy + ez * uz;
-                    const R ed = ex * dx + ey * dy + ez * dz;
-                    feq[i] = wr * ((R)1 + (R)3 * eu + (R)4.5 * eu * eu - usq);
-                    // Eq. 5: f^eq(rho, u + du) - f^eq(rho, u), expanded so that no
-                    // two O(w rho) numbers are subtracted
-                    dF[i] = wr * (ed * ((R)3 + (R)4.5 * ((R)2 * eu + ed)) - dsq);
-                });
+                const R r1u = r * ((R)1 - usq);
+                // Opposite directions i, i+1 (e_{i+1} = -e_i) share the even part
+                // of f^eq and of the forcing term and negate the odd part:
+                //   f^eq_i     = w rho (1 + 4.5 (e.u)^2 - 1.5 u^2) +- 3 w rho e.u
+                //   dF_i (Eq. 5) = f^eq_i(rho, u + du) - f^eq_i(rho, u)
+                //              = w rho (4.5 e.du (2 e.u + e.du) - 1.5 (2 u.du + du^2)) +- 3 w rho e.du
+                // (expanded so that no two O(w rho) numbers are subtracted).
+                // even / odd parts of f^eq (q) and of the forcing term (g) of pair p
+                auto eq_parts = [&](auto PI, R& qs, R& qa) {
+                    constexpr int i = 2 * decltype(PI)::value + 1;
+                    constexpr R w = (R)L::w(i);
+                    const R eu = dot_e<L::ex[i], L::ey[i], L::ez[i]>(ux, uy, uz);
+                    qs = w * r1u + ((R)4.5 * w * r) * (eu * eu);
+                    qa = ((R)3 * w * r) * eu;
+                };
+                auto force_parts = [&](auto PI, R& gs, R& ga) {
+                    constexpr int i = 2 * decltype(PI)::value + 1;
+                    constexpr R w = (R)L::w(i);
+                    const R eu = dot_e<L::ex[i], L::ey[i], L::ez[i]>(ux, uy, uz);
+                    const R ed = dot_e<L::ex[i], L::ey[i], L::ez[i]>(dx, dy, dz);
+                    gs = (w * r) * ((R)4.5 * ed * ((R)2 * eu + ed) - dsq);
+                    ga = ((R)3 * w * r) * ed;
+                };
                 R fo[Q];
                 if constexpr (COLL == COLL_BGK) {
-                    const R om = P.omega[k];
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) fo[i] = f[k][i] - om * (f[k][i] - feq[i]) + dF[i];
+                    // f* = f - omega (f - f^eq) + dF
+                    const R om = P.omega[k], om1 = (R)1 - om;
+                    sfor<NP>([&](auto PI) {
+                        constexpr int p = decltype(PI)::value;
+                        constexpr int i = 2 * p + 1;
+                        R qs, qa, fs, fa;
+                        eq_parts(PI, qs, qa);
+                        force_parts(PI, fs, fa);
+                        const R gs = om * qs + fs;
+                        const R ga = om * qa + fa;
+                        fo[i] = om1 * f[k][i] + (gs + ga);
+                        fo[i + 1] = om1 * f[k][i + 1] + (gs - ga);
+                    });
                 } else {
-                    R d[Q], m[Q];
+                    // f* = f - M^-1 S M (f - f^eq) + dF with M^-1 = M^T diag(1/|row|^2)
+                    // (folded into srate).  Even rows see only d_i + d_{i+1}, odd
+                    // rows only d_i - d_{i+1}.  The density row of f - f^eq is zero,
+                    // and so are the momentum rows when f^eq takes u = j / rho (one
+                    // component); those rows are skipped.
+                    R dp[NP], dm[NP];
+                    sfor<NP>([&](auto PI) {
+                        constexpr int p = decltype(PI)::value;
+                        constexpr int i = 2 * p + 1;
+                        R qs, qa;
+                        eq_parts(PI, qs, qa);
+                        dp[p] = (f[k][i] + f[k][i + 1]) - (R)2 * qs;
+                        dm[p] = (f[k][i] - f[k][i + 1]) - (R)2 * qa;
+                    });
+                    const R d0 = f[k][0] - (R)L::w(0) * r1u;
+                    if constexpr (LAT == LAT_D3Q19) {
+                        R sr[19], E[NP], O[NP];
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) d[i] = f[k][i] - feq[i];
+                        for (int mm = 0; mm < 19; ++mm) sr[mm] = P.srate[k][mm];
+                        mrt_pairs_d3q19<R, (NC > 1)>(dp, dm, d0, sr, E, O);
+                        sfor<NP>([&](auto PI) {
+                            constexpr int p = decltype(PI)::value;
+                            constexpr int i = 2 * p + 1;
+                            R fs, fa;
+                            force_parts(PI, fs, fa);
+                            const R as = fs - E[p], aa = fa - O[p];
+                            fo[i] = f[k][i] + (as + aa);
+                            fo[i + 1] = f[k][i + 1] + (as - aa);
+                        });
+                    } else {
+                    R m[Q];
                     sfor<Q>([&](auto M) {
                         constexpr int mm = decltype(M)::value;
+                        constexpr bool skip = mm == 0 || (NC == 1 && mrt_momentum<LAT>(mm));
+                        constexpr bool even = mrt_even<LAT>(mm);
                         R s = 0;
-                        sfor<Q>([&](auto I) {
-                            constexpr int i = decltype(I)::value;
-                            constexpr double cf = mrt_coef<LAT>(mm, i);
-                            if constexpr (cf == 1.0) s += d[i];
-                            else if constexpr (cf == -1.0) s -= d[i];
-                            else if constexpr (cf != 0.0) s += (R)cf * d[i];
-                        });
-                        m[mm] = s * P.srate[k][mm];
+                        if constexpr (!skip) {
+                            if constexpr (even) {
+                                constexpr double c0 = mrt_coef<LAT>(mm, 0);
+                                if constexpr (c0 != 0.0) s = (R)c0 * d0;
+                            }
+                            sfor<NP>([&](auto PI) {
+                                constexpr int p = decltype(PI)::value;
+                                constexpr double cf = mrt_coef<LAT>(mm, 2 * p + 1);
+                                const R x = even ? dp[p] : dm[p];
+                                if constexpr (cf == 1.0) s += x;
+                                else if constexpr (cf == -1.0) s -= x;
+                                else if constexpr (cf != 0.0) s += (R)cf * x;
+                            });
+                            s *= P.srate[k][mm];
+                        }
+                        m[mm] = s;
                     });
-                    sfor<Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        R s = 0;
+                    sfor<NP>([&](auto PI) {
+                        constexpr int p = decltype(PI)::value;
+                        constexpr int i = 2 * p + 1;
+                        R se = 0, so = 0;
                         sfor<Q>([&](auto M) {
                             constexpr int mm = decltype(M)::value;
+                            constexpr bool skip = mm == 0 || (NC == 1 && mrt_momentum<LAT>(mm));
                             constexpr double cf = mrt_coef<LAT>(mm, i);
-                            if constexpr (cf == 1.0) s += m[mm];
-                            else if constexpr (cf == -1.0) s -= m[mm];
-                            else if constexpr (cf != 0.0) s += (R)cf * m[mm];
+                            if constexpr (!skip && cf != 0.0) {
+                                R& acc = mrt_even<LAT>(mm) ? se : so;
+                                if constexpr (cf == 1.0) acc += m[mm];
+                                else if constexpr (cf == -1.0) acc -= m[mm];
+                                else acc += (R)cf * m[mm];
+                            }
                         });
-                        fo[i] = f[k][i] - s + dF[i];
+                        R fs, fa;
+                        force_parts(PI, fs, fa);
+                        fo[i] = f[k][i] - (se + so) + (fs + fa);
+                        fo[i + 1] = f[k][i + 1] - (se - so) + (fs - fa);
                     });
+                    }
                 }
                 // collision and forcing conserve mass exactly; the rest population
                 // takes the remainder so that sum_i f*_i = rho holds to rounding
@@ -669,21 +936,33 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
                     });
                     fo[0] = r - m;
                 }
-                // store
+                // store: wavefront-uniform base of (component, direction, plane)
+                // plus the 32-bit in-plane offset of the node
+                uint32_t e = (uint32_t)(b * NA + a);
+                asm volatile("" : "+v"(e));
+                const size_t pl = (size_t)c * NA * NB;
+                size_t Ns = N;  // opaque: per-direction bases formed here (see pull_node)
+                asm volatile("" : "+s"(Ns));
+                char* ob = reinterpret_cast<char*>(P.fout);
+                // (the base is pinned in scalar registers so that the per-lane part
+                // is not folded into a shared 64-bit vector address)
+                auto st = [&](char* base, size_t off, auto val) {
+                    using T = decltype(val);
+                    auto bp = (__attribute__((address_space(1))) char*)(base + off);
+                    asm volatile("" : "+s"(bp));
+                    *(__attribute__((address_space(1))) T*)(bp + e * (uint32_t)sizeof(T)) = val;
+                };
                 if constexpr (SS::DEV) {
-                    float* ro = P.rout;
-                    ro[(size_t)k * N + n] = r;
+                    st(reinterpret_cast<char*>(P.rout), ((size_t)k * Ns + pl) * 4, (float)r);
                     const float ir = 1.0f / r;
-                    S* out = reinterpret_cast<S*>(P.fout);
                     sfor<Q>([&](auto I) {
                         constexpr int i = decltype(I)::value;
                         constexpr float iw = (float)(1.0 / L::w(i));
-                        out[(size_t)(k * Q + i) * N + n] = SS::cvt(fo[i] * (iw * ir) - 1.0f);
+                        st(ob, ((size_t)(k * Q + i) * Ns + pl) * sizeof(S), (S)SS::cvt(fo[i] * (iw * ir) - 1.0f));
                     });
                 } else {
-                    S* out = reinterpret_cast<S*>(P.fout);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) out[(size_t)(k * Q + i) * N + n] = fo[i];
+                    for (int i = 0; i < Q; ++i) st(ob, ((size_t)(k * Q + i) * Ns + pl) * sizeof(S), (S)fo[i]);
                 }
             }
         }

@@ -4,13 +4,18 @@ permeability runs.
 
 The paper computes permeability by running the solver from rest to steady
 state and applying Darcy's law, k = nu <u_x> / a (Sec. 3.4.1: 50,000 steps).
-Here the network maps the pore mask to u nu / a; the solver then starts from
-f = f^eq(1, u_pred) and runs to the same residual, so the plain solver
-remains the judge of the permeability.
+Here the network maps the pore mask to the steady fields in units that do not
+depend on the forcing: u nu / a (three channels) and the pressure deviation
+(rho - 1) c_s^2 / a (one channel, a length).  The solver then starts from
+f = f^eq(rho_pred, u_pred - a/2) and runs to the same stopping rule, so the
+plain solver remains the judge of the permeability.  The pressure channel
+matters: the steady density is not uniform (about +-0.2 % in these packs),
+and a start from the exact velocity with rho = 1 converges no faster than a
+start from rest because the pressure has to build up first.
 
 Network (about 1.3 M parameters; every convolution 3x3x3, periodic):
   encoder  16 -> 16 | pool | 32, 32 | pool | 64, 64 | pool | 128, 128
-  decoder  up | 64 (+ skip) 64 | up | 32 (+ skip) 32 | up | 16 (+ skip) 16 | head 3
+  decoder  up | 64 (+ skip) 64 | up | 32 (+ skip) 32 | up | 16 (+ skip) 16 | head 4
 with ReLU after every convolution but the head.  Forward, backward and Adam
 run in the library's kernels (paper_2506_17713_amd.nn); torch only holds
 memory.
@@ -28,7 +33,8 @@ from . import inputs, lbm, nn
 ARCH = [("enc0a", 1, 16), ("enc0b", 16, 16), ("enc1a", 16, 32), ("enc1b", 32, 32),
         ("enc2a", 32, 64), ("enc2b", 64, 64), ("bota", 64, 128), ("botb", 128, 128),
         ("dec2a", 128, 64), ("dec2b", 64, 64), ("dec1a", 64, 32), ("dec1b", 32, 32),
-        ("dec0a", 32, 16), ("dec0b", 16, 16), ("head", 16, 3)]
+        ("dec0a", 32, 16), ("dec0b", 16, 16), ("head", 16, 4)]
+OUT_CH = 4  # u nu / a (x, y, z), (rho - 1) c_s^2 / a
 
 
 class Surrogate:
@@ -45,7 +51,7 @@ class Surrogate:
             for d in (self.m, self.v):
                 d[name] = (torch.zeros_like(self.W[name]), torch.zeros_like(self.b[name]))
         self.t = 0
-        self.scale = 1.0  # target normalisation (u nu / a per unit output)
+        self.scale = np.ones(OUT_CH)  # per-channel target normalisation
         self.repack()
 
     def n_params(self) -> int:
@@ -150,14 +156,23 @@ class Surrogate:
         self.repack()
 
     def predict(self, mask: torch.Tensor) -> np.ndarray:
-        """u nu / a on the host, float64 [3, D, H, W], zero in solids."""
+        """Steady fields on the host, float64 [4, D, H, W], zero in solids:
+        u nu / a (channels 0-2) and (rho - 1) c_s^2 / a (channel 3)."""
         out = self.forward(mask)
-        return out.cpu().numpy().astype(np.float64) * self.scale * mask.cpu().numpy()
+        return out.cpu().numpy().astype(np.float64) * self.scale[:, None, None, None] * mask.cpu().numpy()
 
     def state(self) -> dict:
         return {"scale": self.scale, "t": self.t,
                 **{f"W_{n}": self.W[n].cpu().numpy() for n, _, _ in ARCH},
                 **{f"b_{n}": self.b[n].cpu().numpy() for n, _, _ in ARCH}}
+
+    def load_state(self, st: dict) -> None:
+        self.scale = np.asarray(st["scale"], dtype=np.float64)
+        self.t = int(st["t"])
+        for n, _, _ in ARCH:
+            self.W[n].copy_(torch.as_tensor(np.asarray(st[f"W_{n}"]), dtype=torch.float32))
+            self.b[n].copy_(torch.as_tensor(np.asarray(st[f"b_{n}"]), dtype=torch.float32))
+        self.repack()
 
 
 # ---------------------------------------------------------------------------
@@ -166,47 +181,93 @@ class Surrogate:
 NU = (1.0 - 0.5) / 3.0  # BGK tau = 1
 
 
-def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, tol=1e-6, check=100, max_steps=100000, device="cuda",
-                 storage="F64"):
-    """Run single-phase flow (BGK tau = 1, rho = 1, body acceleration along x)
-    until the residual sum|u_x(t) - u_x(t-100)| / sum|u_x| < tol.
-    FP64 populations by default: with u ~ 1e-4 the FP32 rounding noise of the
-    velocity alone keeps this residual near 3e-5.
-    Returns dict(u [3, N] torch tensor, steps, seconds, k, residual)."""
+def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, rho0=None, tol=1e-6, check=100, max_steps=100000,
+                 device="cuda", storage="F64", k_tol=1e-4):
+    """Run single-phase flow (BGK tau = 1, body acceleration along x) from
+    f^eq(rho0, u0) (rest at rho = 1 by default) until the residual
+    sum|u_x(t) - u_x(t-100)| / sum|u_x| < tol.  FP64 populations by default:
+    with u ~ 1e-4 the FP32 rounding noise of the velocity alone keeps this
+    residual near 3e-5.
+
+    Along the way it records when the permeability estimate k(t) first
+    changed by less than k_tol (relative) over two consecutive checks: the
+    time-to-permeability stopping rule, which needs no converged answer.
+    Returns dict(u [3, N] and rho [N] torch tensors, steps, seconds, k,
+    residual, k_steps, k_seconds, k_at_k_steps, history)."""
     w, solid, rho = inputs.single_phase_pack(shape=solid.shape, solid=solid, accel=accel, storage=storage)
+    if rho0 is not None:
+        rho = np.asarray(rho0, dtype=np.float64).reshape(rho.shape)
+    porosity = float((solid == 0).mean())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sol = lbm.Solver(w, solid, rho, u0=u0, device=device)
     sol.stats()  # first reduction sets the reference velocity
-    steps, res = 0, 1.0
+    steps, res, calm = 0, 1.0, 0
+    hist, k_prev, k_hit = [], None, None
     while steps < max_steps:
         sol.step(check)
         steps += check
         st = sol.stats()
         res = st["residual"]
+        k = NU * st["mean_ux"] * porosity / accel
+        now = time.perf_counter() - t0
+        hist.append((steps, res, k))
+        if k_prev is not None and abs(k - k_prev) < k_tol * abs(k):
+            calm += 1
+            if calm == 2 and k_hit is None:
+                k_hit = (steps, now, k)
+        else:
+            calm = 0
+        k_prev = k
         if res < tol:
             break
-    _, u = sol.moments(-1, rho=False)
+    r, u = sol.moments(0)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    porosity = float((solid == 0).mean())
-    k = NU * st["mean_ux"] * porosity / accel
     sol.close()
-    return {"u": u, "steps": steps, "seconds": secs, "k": k, "residual": res}
+    if k_hit is None:
+        k_hit = (steps, secs, k)
+    return {"u": u, "rho": r, "steps": steps, "seconds": secs, "k": k, "residual": res,
+            "k_steps": k_hit[0], "k_seconds": k_hit[1], "k_at_k_steps": k_hit[2], "history": hist}
 
 
-def make_dataset(n_samples: int, size=128, seed0=0, accel=1e-5, log=print, device="cuda"):
-    """Seeded packs (radii 6-14, porosity U(0.3, 0.5)) and their steady u nu / a."""
+def targets_of(sol_out: dict, solid: np.ndarray, accel: float) -> np.ndarray:
+    """Network targets from a steady solution, computed on the host: u nu / a
+    and (rho - 1) c_s^2 / a at pore nodes (zero in solids), float32
+    [4, D, H, W]."""
+    shape = solid.shape
+    fl = (solid == 0)
+    u = sol_out["u"].cpu().numpy().astype(np.float64).reshape((3,) + shape) * (NU / accel)
+    p = (sol_out["rho"].cpu().numpy().astype(np.float64).reshape(shape) - 1.0) / (3.0 * accel)
+    return (np.concatenate([u, p[None]]) * fl).astype(np.float32)
+
+
+def warm_fields(pred: np.ndarray, solid: np.ndarray, accel: float):
+    """Initial (rho0 [1, N], u0 [3, N]) for the solver from predicted fields
+    (Surrogate.predict units): the pressure channel is shifted to zero mean
+    over the pores so the start holds the same mass as rho = 1, and the
+    velocity is turned into the equilibrium velocity j/rho = u - F/(2 rho)."""
+    fl = (solid == 0).reshape(-1)
+    u = pred[:3].reshape(3, -1) * (accel / NU)
+    u[0] -= 0.5 * accel
+    u *= fl
+    p = pred[3].reshape(-1).copy()
+    p -= p[fl].mean()
+    rho = np.where(fl, 1.0 + 3.0 * accel * p, 1.0)
+    return rho[None], u
+
+
+def make_dataset(n_samples: int, size=128, seed0=0, accel=1e-5, log=print, device="cuda",
+                 radii=(6.0, 14.0)):
+    """Seeded packs (porosity U(0.3, 0.5)) and their steady fields (targets_of)."""
     xs, ys, info = [], [], []
     rng = np.random.default_rng(12345)
     for s in range(n_samples):
         por = float(rng.uniform(0.3, 0.5))
-        solid = inputs.sphere_pack((size,) * 3, (6.0, 14.0), por, seed0 + s)
+        solid = inputs.sphere_pack((size,) * 3, radii, por, seed0 + s)
         r = solve_steady(solid, accel=accel, device=device)
-        mask = torch.tensor((solid == 0).astype(np.float32)[None], device=device)
-        target = r["u"].cpu().numpy().astype(np.float64).reshape(3, size, size, size) * (NU / accel)
-        xs.append(mask)
-        ys.append(target)
+        xs.append(torch.tensor((solid == 0).astype(np.float32)[None], device=device))
+        ys.append(targets_of(r, solid, accel))
         info.append({"seed": seed0 + s, "porosity": float((solid == 0).mean()), "steps": r["steps"],
                      "seconds": r["seconds"], "k": r["k"]})
         log(f"sample {s}: porosity {info[-1]['porosity']:.3f} steps {r['steps']} k {r['k']:.4f} "
@@ -215,11 +276,14 @@ def make_dataset(n_samples: int, size=128, seed0=0, accel=1e-5, log=print, devic
 
 
 def train(model: Surrogate, xs, ys, epochs: int, lr=1e-3, log=print, seed=0):
-    """ys: host float64 targets u nu / a [3, D, H, W]; normalised to unit RMS
-    over pore voxels on the host and kept on the device in FP32."""
-    s2 = sum(float((y * y).sum()) for y in ys) / sum(3.0 * float(x.sum()) for x in xs)
-    model.scale = math.sqrt(s2)
-    ys_n = [torch.tensor((y / model.scale).astype(np.float32), device=xs[0].device) for y in ys]
+    """xs: device masks [1, D, H, W]; ys: host float32 targets [4, D, H, W]
+    (targets_of).  Each channel is normalised on the host to unit RMS over the
+    pore voxels of the whole set, then the set is uploaded once."""
+    npore = sum(float(x.sum()) for x in xs)
+    s2 = sum((y.astype(np.float64) ** 2).sum(axis=(1, 2, 3)) for y in ys) / npore
+    model.scale = np.sqrt(np.maximum(s2, 1e-30))
+    inv = (1.0 / model.scale)[:, None, None, None]
+    ys_n = [torch.tensor((y * inv).astype(np.float32), device=xs[0].device) for y in ys]
     order = np.random.default_rng(seed).permutation
     hist = []
     for ep in range(epochs):
