@@ -434,6 +434,56 @@ __device__ __forceinline__ void pull_node(const StepArgs<typename Store<ST>::R>&
 }
 
 // ---------------------------------------------------------------------------
+// Staged pull (single precision, 3-D): the 19 streaming loads of a node are
+// issued as loads straight into LDS (one dword per lane at consecutive LDS
+// addresses of the wavefront), so a whole plane can be in flight while the
+// previous one is collided without holding any vector registers.  `dst(i)`
+// gives the wavefront-uniform LDS row of direction i.
+// ---------------------------------------------------------------------------
+template <int LAT, class DST>
+__device__ __forceinline__ void stage_pull(const StepArgs<float>& P, int a, int b, int c, DST&& dst) {
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q;
+    const int NA = P.NA, NB = P.NB, NCc = P.NC_;
+    const size_t plane = (size_t)NA * NB;
+    size_t N = (size_t)P.N;
+    asm volatile("" : "+s"(N));
+    const uint32_t col[3] = {(uint32_t)(a == NA - 1 ? 0 : a + 1), (uint32_t)a, (uint32_t)(a == 0 ? NA - 1 : a - 1)};
+    const uint32_t row[3] = {(uint32_t)((b == NB - 1 ? 0 : b + 1) * NA), (uint32_t)(b * NA),
+                             (uint32_t)((b == 0 ? NB - 1 : b - 1) * NA)};
+    const size_t cs[3] = {(size_t)(c == NCc - 1 ? 0 : c + 1), (size_t)c, (size_t)(c == 0 ? NCc - 1 : c - 1)};
+    const char* fb = reinterpret_cast<const char*>(P.fin);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        uint32_t e = row[L::eb(i) + 1] + col[L::ea(i) + 1];
+        asm volatile("" : "+v"(e));
+        const char* base = fb + ((size_t)i * N + cs[L::ec(i) + 1] * plane) * 4;
+        __builtin_amdgcn_global_load_lds((const void*)(base + e * 4u), (void*)dst(i), 4, 0, 0);
+    });
+}
+
+// Halfway bounce-back of a staged node: f_i(x) = f*_opp(i)(x) where x - e_i
+// is solid (the staged value came from a solid node and is not used).
+template <int LAT>
+__device__ __forceinline__ void stage_bounce(const StepArgs<float>& P, int a, int b, int c, uint32_t word,
+                                             float (&f)[Lat<LAT>::Q]) {
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q;
+    if (!(word & ~1u)) return;
+    const size_t plane = (size_t)P.NA * P.NB;
+    const size_t N = (size_t)P.N;
+    uint32_t e = (uint32_t)(b * P.NA + a);
+    asm volatile("" : "+v"(e));
+    const char* fb = reinterpret_cast<const char*>(P.fin);
+    sfor<Q - 1>([&](auto I) {
+        constexpr int i = decltype(I)::value + 1;
+        constexpr int o = opp(i);
+        if ((word >> i) & 1u)
+            f[i] = *reinterpret_cast<const float*>(fb + ((size_t)o * N + (size_t)c * plane) * 4 + e * 4u);
+    });
+}
+
+// ---------------------------------------------------------------------------
 // Pseudopotential (Eq. 12): psi = sqrt(2 (alpha p_CS - c_s^2 rho) / g_kk),
 // U = alpha p_CS - c_s^2 rho; psi = rho for the density pseudopotential.
 // ---------------------------------------------------------------------------
@@ -470,6 +520,21 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
 #ifndef LBM_WAVES_PER_EU
 #define LBM_WAVES_PER_EU 1
 #endif
+#ifndef LBM_LDS_PREFETCH
+#define LBM_LDS_PREFETCH 0
+#endif
+// Workgroup barrier for the LDS rings only: waits for this wavefront's LDS
+// operations, not for its outstanding global loads.  (__syncthreads also
+// waits for loads that write LDS directly, which would drain the staged pull
+// of the next plane at every barrier; the stage is read only by the
+// wavefront that loaded it, after the compiler's own wait for those loads.)
+__device__ __forceinline__ void ring_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 template <int LAT, int NC, int ST, int COLL, bool MOM, int TA, int TB, bool CARRY>
 __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
     k_step(StepArgs<typename Store<ST>::R> P) {
@@ -485,6 +550,11 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
     constexpr int RWA = TA + 4, RWB = TB + 2 * H2B, RP = RWA * RWB;
     constexpr int PWA = TA + 2, PWB = TB + 2 * H1B, PP = PWA * PWB;
 
+    // staged pull of the next plane (own nodes, psi-ring halo positions)
+    constexpr bool LDSP = LBM_LDS_PREFETCH && ST == ST_F32 && D3 && CARRY && !MOM && NC == 1;
+    constexpr int H1W = D3 ? ((2 * (TA + 2) + 2 * TB + 63) / 64) * 64 : 64;
+    __shared__ float s_st[LDSP ? Q : 1][LDSP ? NT : 1];
+    __shared__ float s_sth[LDSP ? Q : 1][LDSP ? H1W : 1];
     __shared__ R s_rho[5][NC][RP];  // rho of fluid nodes, -1 at solid nodes
     __shared__ R s_psi[3][NC][PP];
     __shared__ R s_U[3][NC][PP];
@@ -526,6 +596,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
     const int own_idx = (lb_own + H2B) * RWA + la_own + 2;
     constexpr int HALO = RP - NT;
     constexpr int HPT = (HALO + NT - 1) / NT;
+    constexpr int H1N = D3 ? 2 * (TA + 2) + 2 * TB : 0;  // psi-ring positions (3-D)
     int own_a = a0 + la_own, own_b = b0 + lb_own;
     own_a = smallA ? wrap_any(own_a, NA) : wrap_near(own_a, NA);
     own_b = D3 ? (smallB ? wrap_any(own_b, NB) : wrap_near(own_b, NB)) : 0;
@@ -538,7 +609,35 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
         h_on[j] = h < HALO;
         const int hh = h_on[j] ? h : 0;
         int ra, rb;
-        if (hh < TOP) {
+        if constexpr (D3) {
+            // the psi ring (halo 1) first, on the lowest threads, then halo 2
+            if (hh < H1N) {
+                if (hh < TA + 2) {
+                    rb = 1;
+                    ra = 1 + hh;
+                } else if (hh < 2 * (TA + 2)) {
+                    rb = TB + 2;
+                    ra = 1 + hh - (TA + 2);
+                } else {
+                    const int h3 = hh - 2 * (TA + 2);
+                    rb = 2 + h3 / 2;
+                    ra = (h3 & 1) ? TA + 2 : 1;
+                }
+            } else {
+                const int g = hh - H1N;
+                if (g < RWA) {
+                    rb = 0;
+                    ra = g;
+                } else if (g < 2 * RWA) {
+                    rb = RWB - 1;
+                    ra = g - RWA;
+                } else {
+                    const int g3 = g - 2 * RWA;
+                    rb = 1 + g3 / 2;
+                    ra = (g3 & 1) ? RWA - 1 : 0;
+                }
+            }
+        } else if (hh < TOP) {
             rb = hh / RWA;
             ra = hh % RWA;
         } else if (hh < 2 * TOP) {
@@ -563,15 +662,54 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
 #pragma unroll
         for (int j = 0; j < HPT; ++j) w_halo[j] = h_on[j] ? P.nbr[(c * NB + h_b[j]) * NA + h_a[j]] : 0u;
     };
-    auto fill_rho = [&](int cp, R(&fo)[NC][Q]) {
+    // issue the staged pull of plane cp (own node and psi-ring position)
+    auto prefetch = [&](int cp) {
+        if constexpr (LDSP) {
+            static_assert(HPT == 1, "one halo position per thread");
+            const int c = wrap_c(cp);
+            const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index (uniform)
+            // this wavefront's reads of the stage must be complete before it is overwritten
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+            stage_pull<LAT>(P, own_a, own_b, c, [&](int i) { return &s_st[i][wv * 64]; });
+            if (wv * 64 < H1N && tid < H1N)
+                stage_pull<LAT>(P, h_a[0], h_b[0], c, [&](int i) { return &s_sth[i][wv * 64]; });
+        }
+    };
+    auto fill_rho = [&](int cp, R(&fo)[NC][Q], uint32_t& wcarry) {
         const int slot = (cp - c0 + 5) % 5;
         const int c = wrap_c(cp);
         const uint32_t wo = w_own;
+        wcarry = wo;
         uint32_t wh[HPT];
 #pragma unroll
         for (int j = 0; j < HPT; ++j) wh[j] = w_halo[j];
         fetch_words(cp + 1);
-        {
+        if constexpr (LDSP) {
+            // own node
+#pragma unroll
+            for (int i = 0; i < Q; ++i) fo[0][i] = s_st[i][tid];
+            stage_bounce<LAT>(P, own_a, own_b, c, wo, fo[0]);
+            s_rho[slot][0][own_idx] = (wo & 1u) ? (R)-1 : rho_sum(fo, 0);
+            // halo: psi ring from the stage, outer ring pulled when it has a solid neighbour
+            if (h_on[0]) {
+                if (wh[0] & 1u) {
+                    s_rho[slot][0][h_idx[0]] = (R)-1;
+                } else if (tid < H1N) {
+                    R f[1][Q];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) f[0][i] = s_sth[i][tid];
+                    stage_bounce<LAT>(P, h_a[0], h_b[0], c, wh[0], f[0]);
+                    s_rho[slot][0][h_idx[0]] = rho_sum(f, 0);
+                } else if (wh[0] == 0u) {
+                    s_rho[slot][0][h_idx[0]] = (R)0;  // never read
+                } else {
+                    R f[1][Q];
+                    pull_node<LAT, ST, NC>(P, 0, h_a[0], h_b[0], c, wh[0], f);
+                    s_rho[slot][0][h_idx[0]] = rho_sum(f, 0);
+                }
+            }
+            if (cp < c1 + 1) prefetch(cp + 1);
+        } else {
             const int n = (c * NB + own_b) * NA + own_a;
             pull_node<LAT, ST, NC>(P, n, own_a, own_b, c, wo, fo);
             if (wo & 1u) {
@@ -581,7 +719,6 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = rho_sum(fo, k);
             }
-        }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             if (!h_on[j]) continue;
@@ -597,6 +734,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = rho_sum(f, k);
             }
+        }
         }
     };
 
@@ -662,12 +800,13 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
     };
 
     // ---- phase 3: force, collision + EDM, store (or moments) --------------
-    auto collide_f = [&](int c, const R(&f)[NC][Q], bool pulled) {
+    auto collide_f = [&](int c, const R(&f)[NC][Q], bool pulled, uint32_t wcarry) {
         const int la = la_own, lb = lb_own;
         const int a = a0 + la, b = b0 + lb;
         if (a >= NA || b >= NB) return;
         const int n = (c * NB + b) * NA + a;
-        const uint32_t word = P.nbr[n];
+        // with the carry, the neighbour word came with the pull of this plane
+        const uint32_t word = pulled ? P.nbr[n] : wcarry;
         if (word & 1u) {
             if constexpr (MOM) {
                 if (P.mom_rho) P.mom_rho[n] = 0;
@@ -973,16 +1112,20 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
     // plane it; the first four iterations only fill the rings.  One loop body
     // keeps the code small enough for the instruction cache.
     R fc0[NC][Q], fc1[NC][Q], fc2[NC][Q];
+    uint32_t wc0 = 0, wc1 = 0, wc2 = 0;
     fetch_words(c0 - 2);
+    prefetch(c0 - 2);
 #pragma nounroll
     for (int it = c0 - 4; it < c1; ++it) {
-        fill_rho(it + 2, fc2);
-        __syncthreads();
+        fill_rho(it + 2, fc2, wc2);
+        if constexpr (LDSP) ring_barrier();
+        else __syncthreads();
         if (it + 1 >= c0 - 1) fill_psi(it + 1);
-        __syncthreads();
+        if constexpr (LDSP) ring_barrier();
+        else __syncthreads();
         if (it >= c0) {
             if constexpr (CARRY) {
-                collide_f(it, fc0, false);
+                collide_f(it, fc0, false, wc0);
             } else {
                 // re-pull the own node (L2-resident since its ring pull)
                 const int a = a0 + la_own, b = b0 + lb_own;
@@ -990,11 +1133,13 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
                     const int n = (it * NB + b) * NA + a;
                     const uint32_t word = P.nbr[n];
                     if (!(word & 1u)) pull_node<LAT, ST, NC>(P, n, a, b, it, word, fc0);
-                    collide_f(it, fc0, true);
+                    collide_f(it, fc0, true, word);
                 }
             }
         }
         if constexpr (CARRY) {
+            wc0 = wc1;
+            wc1 = wc2;
 #pragma unroll
             for (int k = 0; k < NC; ++k)
 #pragma unroll

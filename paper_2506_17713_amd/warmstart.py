@@ -17,8 +17,9 @@
    cold run at r < 1e-6.  Warm seconds include inference, the download of the
    prediction and the upload of the initial state.
 
---save-model / --load-model split training and evaluation over two runs;
---test-first selects the first held-out seed offset.
+--save-model / --load-model split training and evaluation over runs (with
+--train > 0 a loaded model is trained further); --test-first selects the
+first held-out seed offset.
 """
 from __future__ import annotations
 
@@ -104,7 +105,9 @@ def main(argv=None):
         with np.load(a.load_model, allow_pickle=False) as z:
             model.load_state({k: z[k] for k in z.files})
         summ["model"] = a.load_model
-    else:
+    if a.train > 0:
+        # (with --load-model this continues training from the saved weights;
+        # the Adam moments restart from zero)
         t0 = time.perf_counter()
         xs, ys, info = make_dataset(a.train, a.size, log=log)
         t_data = time.perf_counter() - t0
