@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="after the run, two plain device copies of this many GiB (hardware-counter calibration)")
     return ap.parse_args()
 
 
@@ -160,6 +162,16 @@ def main():
     }
     print(json.dumps(line), flush=True)
     sol.close()
+    if args.copy_gib > 0:
+        # reference traffic for FETCH_SIZE / WRITE_SIZE: each copy reads and
+        # writes exactly copy_gib GiB
+        n = int(args.copy_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# {2} copies of {args.copy_gib} GiB done", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -18,10 +18,10 @@ using namespace lbmi;
 // own-node populations are carried in registers from the pull to the
 // collision.
 #ifndef LBM_TILE_A
-#define LBM_TILE_A 32
+#define LBM_TILE_A 64
 #endif
 #ifndef LBM_TILE_B
-#define LBM_TILE_B 8
+#define LBM_TILE_B 4
 #endif
 #ifndef LBM_CARRY
 #define LBM_CARRY 1

@@ -362,125 +362,95 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
 // vector instruction besides itself.
 // ---------------------------------------------------------------------------
 template <int LAT, int ST, int NC>
-__device__ __forceinline__ void pull_node(const StepArgs<typename Store<ST>::R>& P, int n, int a,
-                                          int b, int c, uint32_t word,
-                                          typename Store<ST>::R (&f)[NC][Lat<LAT>::Q]) {
+struct Pull {
     using L = Lat<LAT>;
     using SS = Store<ST>;
     using S = typename SS::S;
     using R = typename SS::R;
-    constexpr int Q = L::Q;
-    (void)n;
-    const int NA = P.NA, NB = P.NB, NCc = P.NC_;
-    const size_t plane = (size_t)NA * NB;
-    // the direction stride is made opaque here so that the per-direction
-    // bases are formed in the loop by the scalar unit instead of being kept
-    // live across it (which spills scalar registers)
-    size_t N = (size_t)P.N;
-    asm volatile("" : "+s"(N));
-    // source coordinate x - e for e = -1, 0, +1 (index e + 1), periodic
-    const uint32_t col[3] = {(uint32_t)(a == NA - 1 ? 0 : a + 1), (uint32_t)a, (uint32_t)(a == 0 ? NA - 1 : a - 1)};
-    const uint32_t row[3] = {(uint32_t)((b == NB - 1 ? 0 : b + 1) * NA), (uint32_t)(b * NA),
-                             (uint32_t)((b == 0 ? NB - 1 : b - 1) * NA)};
-    const size_t cs[3] = {(size_t)(c == NCc - 1 ? 0 : c + 1), (size_t)c, (size_t)(c == 0 ? NCc - 1 : c - 1)};
-    const char* fb = reinterpret_cast<const char*>(P.fin);
-    const char* rb = reinterpret_cast<const char*>(P.rin);
-    auto ld = [](const char* base, uint32_t off) { return *reinterpret_cast<const S*>(base + off); };
-    auto ldr = [](const char* base, uint32_t off) { return *reinterpret_cast<const float*>(base + off); };
-    // streaming loads do not depend on the neighbour word, so they issue
-    // together with it; a source that is solid holds no population and its
-    // value is replaced by the bounced one below
+    static constexpr int Q = L::Q;
     S v[NC][Q];
-    float rs[NC][Q];
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        uint32_t e = row[L::eb(i) + 1] + col[L::ea(i) + 1];
-        // keep the offset a 32-bit value computed here: hoisted out of the
-        // plane loop it would be widened to 64 bits and the loads would lose
-        // the scalar-base addressing form
-        asm volatile("" : "+v"(e));
-        const size_t pl = cs[L::ec(i) + 1] * plane;
+    float rs[NC][SS::DEV ? Q : 1];
+
+    // Issue the streaming loads f*_i(x - e_i) of node (a, b, c).  They do not
+    // depend on the neighbour word; a source that is solid holds no
+    // population and its value is replaced in finish().
+    __device__ __forceinline__ void issue(const StepArgs<R>& P, int a, int b, int c) {
+        const int NA = P.NA, NB = P.NB, NCc = P.NC_;
+        const size_t plane = (size_t)NA * NB;
+        // the direction stride is made opaque here so that the per-direction
+        // bases are formed in the loop by the scalar unit instead of being
+        // kept live across it (which spills scalar registers)
+        size_t N = (size_t)P.N;
+        asm volatile("" : "+s"(N));
+        // source coordinate x - e for e = -1, 0, +1 (index e + 1), periodic
+        const uint32_t col[3] = {(uint32_t)(a == NA - 1 ? 0 : a + 1), (uint32_t)a,
+                                 (uint32_t)(a == 0 ? NA - 1 : a - 1)};
+        const uint32_t row[3] = {(uint32_t)((b == NB - 1 ? 0 : b + 1) * NA), (uint32_t)(b * NA),
+                                 (uint32_t)((b == 0 ? NB - 1 : b - 1) * NA)};
+        const size_t cs[3] = {(size_t)(c == NCc - 1 ? 0 : c + 1), (size_t)c, (size_t)(c == 0 ? NCc - 1 : c - 1)};
+        const char* fb = reinterpret_cast<const char*>(P.fin);
+        const char* rb = reinterpret_cast<const char*>(P.rin);
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            uint32_t e = row[L::eb(i) + 1] + col[L::ea(i) + 1];
+            // keep the offset a 32-bit value computed here: hoisted out of the
+            // plane loop it would be widened to 64 bits and the loads would lose
+            // the scalar-base addressing form
+            asm volatile("" : "+v"(e));
+            const size_t pl = cs[L::ec(i) + 1] * plane;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            v[k][i] = ld(fb + ((size_t)(k * Q + i) * N + pl) * sizeof(S), e * (uint32_t)sizeof(S));
-            if constexpr (SS::DEV) rs[k][i] = ldr(rb + ((size_t)k * N + pl) * 4, e * 4u);
-        }
-    });
-    if (word & ~1u) {
-        // halfway bounce-back: f_i(x) = f*_opp(i)(x) when x - e_i is solid
-        uint32_t e = row[1] + col[1];
-        asm volatile("" : "+v"(e));
-        const size_t pl = cs[1] * plane;
-        sfor<Q - 1>([&](auto I) {
-            constexpr int i = decltype(I)::value + 1;
-            constexpr int o = opp(i);
-            if ((word >> i) & 1u) {
-#pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    v[k][i] = ld(fb + ((size_t)(k * Q + o) * N + pl) * sizeof(S), e * (uint32_t)sizeof(S));
-                    if constexpr (SS::DEV) rs[k][i] = ldr(rb + ((size_t)k * N + pl) * 4, e * 4u);
-                }
+            for (int k = 0; k < NC; ++k) {
+                v[k][i] = *reinterpret_cast<const S*>(fb + ((size_t)(k * Q + i) * N + pl) * sizeof(S) +
+                                                      e * (uint32_t)sizeof(S));
+                if constexpr (SS::DEV)
+                    rs[k][i] = *reinterpret_cast<const float*>(rb + ((size_t)k * N + pl) * 4 + e * 4u);
             }
         });
     }
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+
+    // Halfway bounce-back (f_i(x) = f*_opp(i)(x) where x - e_i is solid) and
+    // conversion to the compute type.
+    __device__ __forceinline__ void finish(const StepArgs<R>& P, int a, int b, int c, uint32_t word,
+                                           R (&f)[NC][Q]) {
+        if (word & ~1u) {
+            const size_t plane = (size_t)P.NA * P.NB;
+            const size_t N = (size_t)P.N;
+            uint32_t e = (uint32_t)(b * P.NA + a);
+            asm volatile("" : "+v"(e));
+            const size_t pl = (size_t)c * plane;
+            const char* fb = reinterpret_cast<const char*>(P.fin);
+            const char* rb = reinterpret_cast<const char*>(P.rin);
+            sfor<Q - 1>([&](auto I) {
+                constexpr int i = decltype(I)::value + 1;
+                constexpr int o = opp(i);
+                if ((word >> i) & 1u) {
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            if constexpr (SS::DEV) f[k][i] = (float)L::w(i) * rs[k][i] * (1.0f + SS::load(v[k][i]));
-            else f[k][i] = (R)v[k][i];
+                    for (int k = 0; k < NC; ++k) {
+                        v[k][i] = *reinterpret_cast<const S*>(fb + ((size_t)(k * Q + o) * N + pl) * sizeof(S) +
+                                                              e * (uint32_t)sizeof(S));
+                        if constexpr (SS::DEV)
+                            rs[k][i] = *reinterpret_cast<const float*>(rb + ((size_t)k * N + pl) * 4 + e * 4u);
+                    }
+                }
+            });
         }
-    });
-}
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                if constexpr (SS::DEV) f[k][i] = (float)L::w(i) * rs[k][i] * (1.0f + SS::load(v[k][i]));
+                else f[k][i] = (R)v[k][i];
+            }
+        });
+    }
+};
 
-// ---------------------------------------------------------------------------
-// Staged pull (single precision, 3-D): the 19 streaming loads of a node are
-// issued as loads straight into LDS (one dword per lane at consecutive LDS
-// addresses of the wavefront), so a whole plane can be in flight while the
-// previous one is collided without holding any vector registers.  `dst(i)`
-// gives the wavefront-uniform LDS row of direction i.
-// ---------------------------------------------------------------------------
-template <int LAT, class DST>
-__device__ __forceinline__ void stage_pull(const StepArgs<float>& P, int a, int b, int c, DST&& dst) {
-    using L = Lat<LAT>;
-    constexpr int Q = L::Q;
-    const int NA = P.NA, NB = P.NB, NCc = P.NC_;
-    const size_t plane = (size_t)NA * NB;
-    size_t N = (size_t)P.N;
-    asm volatile("" : "+s"(N));
-    const uint32_t col[3] = {(uint32_t)(a == NA - 1 ? 0 : a + 1), (uint32_t)a, (uint32_t)(a == 0 ? NA - 1 : a - 1)};
-    const uint32_t row[3] = {(uint32_t)((b == NB - 1 ? 0 : b + 1) * NA), (uint32_t)(b * NA),
-                             (uint32_t)((b == 0 ? NB - 1 : b - 1) * NA)};
-    const size_t cs[3] = {(size_t)(c == NCc - 1 ? 0 : c + 1), (size_t)c, (size_t)(c == 0 ? NCc - 1 : c - 1)};
-    const char* fb = reinterpret_cast<const char*>(P.fin);
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        uint32_t e = row[L::eb(i) + 1] + col[L::ea(i) + 1];
-        asm volatile("" : "+v"(e));
-        const char* base = fb + ((size_t)i * N + cs[L::ec(i) + 1] * plane) * 4;
-        __builtin_amdgcn_global_load_lds((const void*)(base + e * 4u), (void*)dst(i), 4, 0, 0);
-    });
-}
-
-// Halfway bounce-back of a staged node: f_i(x) = f*_opp(i)(x) where x - e_i
-// is solid (the staged value came from a solid node and is not used).
-template <int LAT>
-__device__ __forceinline__ void stage_bounce(const StepArgs<float>& P, int a, int b, int c, uint32_t word,
-                                             float (&f)[Lat<LAT>::Q]) {
-    using L = Lat<LAT>;
-    constexpr int Q = L::Q;
-    if (!(word & ~1u)) return;
-    const size_t plane = (size_t)P.NA * P.NB;
-    const size_t N = (size_t)P.N;
-    uint32_t e = (uint32_t)(b * P.NA + a);
-    asm volatile("" : "+v"(e));
-    const char* fb = reinterpret_cast<const char*>(P.fin);
-    sfor<Q - 1>([&](auto I) {
-        constexpr int i = decltype(I)::value + 1;
-        constexpr int o = opp(i);
-        if ((word >> i) & 1u)
-            f[i] = *reinterpret_cast<const float*>(fb + ((size_t)o * N + (size_t)c * plane) * 4 + e * 4u);
-    });
+template <int LAT, int ST, int NC>
+__device__ __forceinline__ void pull_node(const StepArgs<typename Store<ST>::R>& P, int a, int b, int c,
+                                          uint32_t word, typename Store<ST>::R (&f)[NC][Lat<LAT>::Q]) {
+    Pull<LAT, ST, NC> pu;
+    pu.issue(P, a, b, c);
+    pu.finish(P, a, b, c, word, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -517,23 +487,11 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
 // ---------------------------------------------------------------------------
 // The fused step (MOM = false) or the moment evaluation (MOM = true).
 // ---------------------------------------------------------------------------
+// Minimum waves per SIMD the register allocator must allow (1: no bound;
+// the one-component single-precision kernels fit three waves by themselves).
 #ifndef LBM_WAVES_PER_EU
 #define LBM_WAVES_PER_EU 1
 #endif
-#ifndef LBM_LDS_PREFETCH
-#define LBM_LDS_PREFETCH 0
-#endif
-// Workgroup barrier for the LDS rings only: waits for this wavefront's LDS
-// operations, not for its outstanding global loads.  (__syncthreads also
-// waits for loads that write LDS directly, which would drain the staged pull
-// of the next plane at every barrier; the stage is read only by the
-// wavefront that loaded it, after the compiler's own wait for those loads.)
-__device__ __forceinline__ void ring_barrier() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
 template <int LAT, int NC, int ST, int COLL, bool MOM, int TA, int TB, bool CARRY>
 __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
@@ -550,11 +508,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
     constexpr int RWA = TA + 4, RWB = TB + 2 * H2B, RP = RWA * RWB;
     constexpr int PWA = TA + 2, PWB = TB + 2 * H1B, PP = PWA * PWB;
 
-    // staged pull of the next plane (own nodes, psi-ring halo positions)
-    constexpr bool LDSP = LBM_LDS_PREFETCH && ST == ST_F32 && D3 && CARRY && !MOM && NC == 1;
-    constexpr int H1W = D3 ? ((2 * (TA + 2) + 2 * TB + 63) / 64) * 64 : 64;
-    __shared__ float s_st[LDSP ? Q : 1][LDSP ? NT : 1];
-    __shared__ float s_sth[LDSP ? Q : 1][LDSP ? H1W : 1];
+    __shared__ uint32_t s_word[3][NT];  // own-node neighbour words of the carried planes
     __shared__ R s_rho[5][NC][RP];  // rho of fluid nodes, -1 at solid nodes
     __shared__ R s_psi[3][NC][PP];
     __shared__ R s_U[3][NC][PP];
@@ -662,79 +616,62 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
 #pragma unroll
         for (int j = 0; j < HPT; ++j) w_halo[j] = h_on[j] ? P.nbr[(c * NB + h_b[j]) * NA + h_a[j]] : 0u;
     };
-    // issue the staged pull of plane cp (own node and psi-ring position)
-    auto prefetch = [&](int cp) {
-        if constexpr (LDSP) {
-            static_assert(HPT == 1, "one halo position per thread");
-            const int c = wrap_c(cp);
-            const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index (uniform)
-            // this wavefront's reads of the stage must be complete before it is overwritten
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-            stage_pull<LAT>(P, own_a, own_b, c, [&](int i) { return &s_st[i][wv * 64]; });
-            if (wv * 64 < H1N && tid < H1N)
-                stage_pull<LAT>(P, h_a[0], h_b[0], c, [&](int i) { return &s_sth[i][wv * 64]; });
-        }
-    };
-    auto fill_rho = [&](int cp, R(&fo)[NC][Q], uint32_t& wcarry) {
+    auto fill_rho = [&](int cp, R(&fo)[NC][Q]) {
         const int slot = (cp - c0 + 5) % 5;
         const int c = wrap_c(cp);
         const uint32_t wo = w_own;
-        wcarry = wo;
+        s_word[(cp - c0 + 3) % 3][tid] = wo;  // read back by this thread at the plane's collision
         uint32_t wh[HPT];
 #pragma unroll
         for (int j = 0; j < HPT; ++j) wh[j] = w_halo[j];
         fetch_words(cp + 1);
-        if constexpr (LDSP) {
-            // own node
+        // A halo position is pulled unless it is solid, or it lies on the
+        // outer ring (halo 2, which feeds only virtual densities) without a
+        // solid neighbour.
+        auto need = [&](int j) { return h_on[j] && !(wh[j] & 1u) && !(h_outer[j] && wh[j] == 0u); };
+        // With plain storage and BGK all loads of the plane are issued before
+        // any is waited for, so the halo pulls do not add a second memory
+        // latency.  MRT (whose collision needs more registers) and deviation
+        // storage (which also loads rho* per direction) keep the sequential
+        // order: with two nodes in flight they no longer fit three waves per
+        // SIMD without spilling, which costs more than the latency saved.
+        constexpr bool OVERLAP = !SS::DEV && COLL == COLL_BGK;
+        Pull<LAT, ST, NC> po;
+        Pull<LAT, ST, NC> ph[OVERLAP ? HPT : 1];
+        po.issue(P, own_a, own_b, c);
+        if constexpr (OVERLAP) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) fo[0][i] = s_st[i][tid];
-            stage_bounce<LAT>(P, own_a, own_b, c, wo, fo[0]);
-            s_rho[slot][0][own_idx] = (wo & 1u) ? (R)-1 : rho_sum(fo, 0);
-            // halo: psi ring from the stage, outer ring pulled when it has a solid neighbour
-            if (h_on[0]) {
-                if (wh[0] & 1u) {
-                    s_rho[slot][0][h_idx[0]] = (R)-1;
-                } else if (tid < H1N) {
-                    R f[1][Q];
+            for (int j = 0; j < HPT; ++j)
+                if (need(j)) ph[j].issue(P, h_a[j], h_b[j], c);
+        }
+        po.finish(P, own_a, own_b, c, wo, fo);
+        if (wo & 1u) {
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) f[0][i] = s_sth[i][tid];
-                    stage_bounce<LAT>(P, h_a[0], h_b[0], c, wh[0], f[0]);
-                    s_rho[slot][0][h_idx[0]] = rho_sum(f, 0);
-                } else if (wh[0] == 0u) {
-                    s_rho[slot][0][h_idx[0]] = (R)0;  // never read
-                } else {
-                    R f[1][Q];
-                    pull_node<LAT, ST, NC>(P, 0, h_a[0], h_b[0], c, wh[0], f);
-                    s_rho[slot][0][h_idx[0]] = rho_sum(f, 0);
-                }
-            }
-            if (cp < c1 + 1) prefetch(cp + 1);
+            for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = (R)-1;
         } else {
-            const int n = (c * NB + own_b) * NA + own_a;
-            pull_node<LAT, ST, NC>(P, n, own_a, own_b, c, wo, fo);
-            if (wo & 1u) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = (R)-1;
-            } else {
-#pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = rho_sum(fo, k);
-            }
+            for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = rho_sum(fo, k);
+        }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             if (!h_on[j]) continue;
             if (wh[j] & 1u) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = (R)-1;
-            } else if (h_outer[j] && wh[j] == 0u) {
+            } else if (!need(j)) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = (R)0;  // never read
             } else {
                 R f[NC][Q];
-                pull_node<LAT, ST, NC>(P, (c * NB + h_b[j]) * NA + h_a[j], h_a[j], h_b[j], c, wh[j], f);
+                if constexpr (OVERLAP) {
+                    ph[j].finish(P, h_a[j], h_b[j], c, wh[j], f);
+                } else {
+                    ph[0].issue(P, h_a[j], h_b[j], c);
+                    ph[0].finish(P, h_a[j], h_b[j], c, wh[j], f);
+                }
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = rho_sum(f, k);
             }
-        }
         }
     };
 
@@ -800,13 +737,13 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
     };
 
     // ---- phase 3: force, collision + EDM, store (or moments) --------------
-    auto collide_f = [&](int c, const R(&f)[NC][Q], bool pulled, uint32_t wcarry) {
+    auto collide_f = [&](int c, const R(&f)[NC][Q], bool pulled, uint32_t wpull) {
         const int la = la_own, lb = lb_own;
         const int a = a0 + la, b = b0 + lb;
         if (a >= NA || b >= NB) return;
         const int n = (c * NB + b) * NA + a;
         // with the carry, the neighbour word came with the pull of this plane
-        const uint32_t word = pulled ? P.nbr[n] : wcarry;
+        const uint32_t word = pulled ? wpull : s_word[(c - c0 + 3) % 3][tid];
         if (word & 1u) {
             if constexpr (MOM) {
                 if (P.mom_rho) P.mom_rho[n] = 0;
@@ -1112,34 +1049,28 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
     // plane it; the first four iterations only fill the rings.  One loop body
     // keeps the code small enough for the instruction cache.
     R fc0[NC][Q], fc1[NC][Q], fc2[NC][Q];
-    uint32_t wc0 = 0, wc1 = 0, wc2 = 0;
     fetch_words(c0 - 2);
-    prefetch(c0 - 2);
 #pragma nounroll
     for (int it = c0 - 4; it < c1; ++it) {
-        fill_rho(it + 2, fc2, wc2);
-        if constexpr (LDSP) ring_barrier();
-        else __syncthreads();
+        fill_rho(it + 2, fc2);
+        __syncthreads();
         if (it + 1 >= c0 - 1) fill_psi(it + 1);
-        if constexpr (LDSP) ring_barrier();
-        else __syncthreads();
+        __syncthreads();
         if (it >= c0) {
             if constexpr (CARRY) {
-                collide_f(it, fc0, false, wc0);
+                collide_f(it, fc0, false, 0u);
             } else {
                 // re-pull the own node (L2-resident since its ring pull)
                 const int a = a0 + la_own, b = b0 + lb_own;
                 if (a < NA && b < NB) {
                     const int n = (it * NB + b) * NA + a;
                     const uint32_t word = P.nbr[n];
-                    if (!(word & 1u)) pull_node<LAT, ST, NC>(P, n, a, b, it, word, fc0);
+                    if (!(word & 1u)) pull_node<LAT, ST, NC>(P, a, b, it, word, fc0);
                     collide_f(it, fc0, true, word);
                 }
             }
         }
         if constexpr (CARRY) {
-            wc0 = wc1;
-            wc1 = wc2;
 #pragma unroll
             for (int k = 0; k < NC; ++k)
 #pragma unroll
