@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--storage", default="F32", choices=["F32", "F64", "F16DEV", "BF16DEV"])
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="after the run, two plain device copies of this many GiB (hardware-counter calibration)")
     return ap.parse_args()
@@ -86,9 +86,9 @@ def cpu_baseline(budget_s: float) -> dict:
     st = oracle.State(w, solid, rho)
     st.step(1)
     t0 = time.perf_counter()
-    st.step(2)
-    dt2 = time.perf_counter() - t0
-    k = max(2, int(budget_s / max(dt2 / 2, 1e-6)))
+    st.step(5)
+    dt5 = time.perf_counter() - t0
+    k = max(2, int(budget_s / max(dt5 / 5, 1e-6)))
     t0 = time.perf_counter()
     st.step(k)
     dt = time.perf_counter() - t0

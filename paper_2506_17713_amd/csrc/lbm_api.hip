@@ -129,11 +129,13 @@ void fill_args(lbm_handle* h, StepArgs<R>& a, const Buffers* bufs) {
     a.NC_ = h->NCc;
     a.N = h->N;
     a.common_u = p.common_velocity ? 1 : 0;
+    a.wet_uniform = h->wet_uniform ? 1 : 0;
     a.has_zc = 0;
     const int q = q_of(p.lattice);
     for (int k = 0; k < p.n_comp; ++k) {
         a.psi_cs[k] = p.psi_kind[k] == LBM_PSI_CS;
         a.wet_drho[k] = p.wet_mode[k] == LBM_WET_DRHO;
+        a.wet_val[k] = (R)p.wet[k];
         a.omega[k] = (R)(1.0 / p.tau[k]);
         for (int m = 0; m < q; ++m) {
             const double nrm = p.lattice == LBM_D2Q9 ? mrt_norm<LAT_D2Q9>(m) : mrt_norm<LAT_D3Q19>(m);
@@ -432,6 +434,7 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     h->step = 0;
     h->since_check = 0;
     h->have_prev = false;
+    h->wet_uniform = wet == nullptr;
     const char* ch = std::getenv("LBM_CHUNK");
     h->chunk_override = ch ? std::atoi(ch) : 0;
 

@@ -330,6 +330,8 @@ struct StepArgs {
     int N;                 // nodes
     int psi_cs[2];         // 1: Carnahan-Starling pseudopotential, 0: psi = rho
     int wet_drho[2];       // 1: rho_ave - drho, 0: phi * rho_ave
+    int wet_uniform;       // 1: the wetting parameter is wet_val[k] at every node
+    R wet_val[2];
     int common_u;          // two components: common equilibrium velocity
     int has_zc;            // any A_kk != 0
     R omega[2];            // 1/tau
@@ -361,7 +363,10 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
 // (e_a, e_b), so nine adds cover all directions and each load costs one
 // vector instruction besides itself.
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, int NC>
+// BBI: take the bounce-back source at issue time (two components, where every
+// gather pays a full memory latency) or patch it after the streaming loads
+// (one component: a cheaper plain path for the bulk).
+template <int LAT, int ST, int NC, bool BBI = (NC > 1)>
 struct Pull {
     using L = Lat<LAT>;
     using SS = Store<ST>;
@@ -371,10 +376,14 @@ struct Pull {
     S v[NC][Q];
     float rs[NC][SS::DEV ? Q : 1];
 
-    // Issue the streaming loads f*_i(x - e_i) of node (a, b, c).  They do not
-    // depend on the neighbour word; a source that is solid holds no
-    // population and its value is replaced in finish().
-    __device__ __forceinline__ void issue(const StepArgs<R>& P, int a, int b, int c) {
+    // Issue the loads of node (a, b, c): f_i(x) = f*_i(x - e_i), or, where
+    // x - e_i is solid (bit i of the neighbour word), the halfway bounce-back
+    // f*_opp(i)(x).  With BBI the source is chosen per lane before the load,
+    // so a node next to a wall costs no second, dependent round of loads (a
+    // wavefront with no such lane takes the plain path); without it the
+    // streaming loads are issued unconditionally and finish() replaces the
+    // values that came from solid nodes.
+    __device__ __forceinline__ void issue(const StepArgs<R>& P, int a, int b, int c, uint32_t word) {
         const int NA = P.NA, NB = P.NB, NCc = P.NC_;
         const size_t plane = (size_t)NA * NB;
         // the direction stride is made opaque here so that the per-direction
@@ -390,29 +399,41 @@ struct Pull {
         const size_t cs[3] = {(size_t)(c == NCc - 1 ? 0 : c + 1), (size_t)c, (size_t)(c == 0 ? NCc - 1 : c - 1)};
         const char* fb = reinterpret_cast<const char*>(P.fin);
         const char* rb = reinterpret_cast<const char*>(P.rin);
+        auto load = [&](int k, int dir, size_t pl, uint32_t e, int i) {
+            v[k][i] = *reinterpret_cast<const S*>(fb + ((size_t)(k * Q + dir) * N + pl) * sizeof(S) +
+                                                  e * (uint32_t)sizeof(S));
+            if constexpr (SS::DEV)
+                rs[k][i] = *reinterpret_cast<const float*>(rb + ((size_t)k * N + pl) * 4 + e * 4u);
+        };
+        const bool wall = BBI && __builtin_amdgcn_ballot_w64((word & ~1u) != 0u) != 0;
         sfor<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
+            // keep offsets 32-bit values computed here: hoisted out of the plane
+            // loop they would be widened to 64 bits and the loads would lose the
+            // scalar-base addressing form
             uint32_t e = row[L::eb(i) + 1] + col[L::ea(i) + 1];
-            // keep the offset a 32-bit value computed here: hoisted out of the
-            // plane loop it would be widened to 64 bits and the loads would lose
-            // the scalar-base addressing form
             asm volatile("" : "+v"(e));
             const size_t pl = cs[L::ec(i) + 1] * plane;
+            if (i == 0 || !wall) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) {
-                v[k][i] = *reinterpret_cast<const S*>(fb + ((size_t)(k * Q + i) * N + pl) * sizeof(S) +
-                                                      e * (uint32_t)sizeof(S));
-                if constexpr (SS::DEV)
-                    rs[k][i] = *reinterpret_cast<const float*>(rb + ((size_t)k * N + pl) * 4 + e * 4u);
+                for (int k = 0; k < NC; ++k) load(k, i, pl, e, i);
+            } else if (!((word >> i) & 1u)) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) load(k, i, pl, e, i);
+            } else {
+                uint32_t eo = row[1] + col[1];
+                asm volatile("" : "+v"(eo));
+#pragma unroll
+                for (int k = 0; k < NC; ++k) load(k, opp(i), cs[1] * plane, eo, i);
             }
         });
     }
 
-    // Halfway bounce-back (f_i(x) = f*_opp(i)(x) where x - e_i is solid) and
-    // conversion to the compute type.
+    // Conversion to the compute type (and, without BBI, the bounce-back
+    // loads after the streaming ones).
     __device__ __forceinline__ void finish(const StepArgs<R>& P, int a, int b, int c, uint32_t word,
                                            R (&f)[NC][Q]) {
-        if (word & ~1u) {
+        if (!BBI && (word & ~1u)) {
             const size_t plane = (size_t)P.NA * P.NB;
             const size_t N = (size_t)P.N;
             uint32_t e = (uint32_t)(b * P.NA + a);
@@ -422,11 +443,10 @@ struct Pull {
             const char* rb = reinterpret_cast<const char*>(P.rin);
             sfor<Q - 1>([&](auto I) {
                 constexpr int i = decltype(I)::value + 1;
-                constexpr int o = opp(i);
                 if ((word >> i) & 1u) {
 #pragma unroll
                     for (int k = 0; k < NC; ++k) {
-                        v[k][i] = *reinterpret_cast<const S*>(fb + ((size_t)(k * Q + o) * N + pl) * sizeof(S) +
+                        v[k][i] = *reinterpret_cast<const S*>(fb + ((size_t)(k * Q + opp(i)) * N + pl) * sizeof(S) +
                                                               e * (uint32_t)sizeof(S));
                         if constexpr (SS::DEV)
                             rs[k][i] = *reinterpret_cast<const float*>(rb + ((size_t)k * N + pl) * 4 + e * 4u);
@@ -449,7 +469,7 @@ template <int LAT, int ST, int NC>
 __device__ __forceinline__ void pull_node(const StepArgs<typename Store<ST>::R>& P, int a, int b, int c,
                                           uint32_t word, typename Store<ST>::R (&f)[NC][Lat<LAT>::Q]) {
     Pull<LAT, ST, NC> pu;
-    pu.issue(P, a, b, c);
+    pu.issue(P, a, b, c, word);
     pu.finish(P, a, b, c, word, f);
 }
 
@@ -540,7 +560,13 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
         return r;
     };
 
-    // ---- phase 1: pull a plane with halo 2, store rho (solid: -1) ---------
+    // Solid positions are marked in the rho ring: -1 for a solid node with a
+    // fluid neighbour (its virtual density is needed), -2 for one whose
+    // neighbours are all solid (its pseudopotential is never read).
+    constexpr uint32_t ALLNB = ((1u << Q) - 1u) & ~1u;
+    auto solid_mark = [](uint32_t word) { return (word & ALLNB) == ALLNB ? (R)-2 : (R)-1; };
+
+    // ---- phase 1: pull a plane with halo 2, store rho (solid: < 0) --------
     // Each thread pulls its own node (kept in registers until its collision
     // two planes later when CARRY) and HPT halo positions.  A halo-2 position
     // (outside the psi halo) only feeds virtual densities and is pulled only
@@ -638,16 +664,16 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
         constexpr bool OVERLAP = !SS::DEV && COLL == COLL_BGK;
         Pull<LAT, ST, NC> po;
         Pull<LAT, ST, NC> ph[OVERLAP ? HPT : 1];
-        po.issue(P, own_a, own_b, c);
+        po.issue(P, own_a, own_b, c, wo);
         if constexpr (OVERLAP) {
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
-                if (need(j)) ph[j].issue(P, h_a[j], h_b[j], c);
+                if (need(j)) ph[j].issue(P, h_a[j], h_b[j], c, wh[j]);
         }
         po.finish(P, own_a, own_b, c, wo, fo);
         if (wo & 1u) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = (R)-1;
+            for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = solid_mark(wo);
         } else {
 #pragma unroll
             for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = rho_sum(fo, k);
@@ -657,7 +683,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
             if (!h_on[j]) continue;
             if (wh[j] & 1u) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = (R)-1;
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = solid_mark(wh[j]);
             } else if (!need(j)) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = (R)0;  // never read
@@ -666,7 +692,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
                 if constexpr (OVERLAP) {
                     ph[j].finish(P, h_a[j], h_b[j], c, wh[j], f);
                 } else {
-                    ph[0].issue(P, h_a[j], h_b[j], c);
+                    ph[0].issue(P, h_a[j], h_b[j], c, wh[j]);
                     ph[0].finish(P, h_a[j], h_b[j], c, wh[j], f);
                 }
 #pragma unroll
@@ -683,7 +709,14 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
             const int pa = idx % PWA, pb = idx / PWA;
             const int ra = pa + 1, rb = pb + (H2B - H1B);
             const R r0 = s_rho[rs0][0][rb * RWA + ra];
-            if (r0 >= (R)0) {
+            if (r0 == (R)-2) {
+                // solid without fluid neighbours
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    s_psi[pslot][k][idx] = 0;
+                    s_U[pslot][k][idx] = 0;
+                }
+            } else if (r0 >= (R)0) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
                     R ps, u;
@@ -716,7 +749,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
 #pragma unroll
                     for (int k = 0; k < NC; ++k) {
                         const R rave = num[k] / den;
-                        const R prm = P.wet[(size_t)k * N + n];
+                        const R prm = P.wet_uniform ? P.wet_val[k] : P.wet[(size_t)k * N + n];
                         R rsv = P.wet_drho[k] ? rave - prm : prm * rave;
                         rsv = rsv < P.rho_min[k] ? P.rho_min[k] : rsv;
                         rsv = rsv > P.rho_max[k] ? P.rho_max[k] : rsv;

@@ -47,6 +47,7 @@ struct lbm_handle {
     int64_t step;
     int64_t since_check;
     bool have_prev;
+    bool wet_uniform;  // no per-node wetting field was given: p.wet[k] everywhere
     int chunk_override;
 };
 
