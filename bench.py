@@ -7,6 +7,10 @@ virtual-density wetting (phi = 1.1).  A step is one launch of the fused
 kernel (moments, virtual densities, pseudopotential, force, MRT collision with
 exact-difference forcing, pull streaming with bounce-back).
 
+--workload droplet2d (D2Q9 BGK FP64 droplet, 128^2) and --workload pack2
+(two-component D3Q19 sphere pack, 400^3, BGK) time the other configurations
+the same way.
+
 Prints one JSON line: MLUPS (n_components * nx * ny * nz * steps / time / 1e6,
 all nodes counted as the paper does), the HBM roofline of the fused kernel
 (algorithmic bytes per launch / mean launch time from HIP events on the
@@ -33,7 +37,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n", type=int, default=None, help="lattice size (default: 256, 128 for droplet2d, "
+                                                         "400 for pack2)")
+    ap.add_argument("--workload", default="sessile", choices=["sessile", "droplet2d", "pack2"],
+                    help="sessile: D3Q19 MRT sessile droplet (the headline line); droplet2d: D2Q9 BGK FP64 "
+                         "droplet; pack2: D3Q19 two-component sphere pack")
     ap.add_argument("--storage", default="F32", choices=["F32", "F64", "F16DEV", "BF16DEV"])
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -58,7 +66,7 @@ def algorithmic_bytes(w, solid) -> float:
     return float(n_fluid * per_fluid + w.N)
 
 
-def measured_traffic(w) -> float | None:
+def measured_traffic(w, name: str) -> float | None:
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
     measurement (profiles/k_step_traffic.json), scaled by the same counters on
     a 1 GiB copy; None if the kernel sources changed since, or for another
@@ -66,7 +74,8 @@ def measured_traffic(w) -> float | None:
     import hashlib
 
     path = ROOT / "profiles" / "k_step_traffic.json"
-    if not path.exists() or w.storage != "F32" or w.collision != "MRT" or w.shape != (256, 256, 256):
+    if (not path.exists() or name != "sessile" or w.storage != "F32" or w.collision != "MRT"
+            or w.shape != (256, 256, 256)):
         return None
     rec = json.loads(path.read_text())
     h = hashlib.sha256()
@@ -75,14 +84,34 @@ def measured_traffic(w) -> float | None:
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["kernel_source_sha256"] else None
 
 
-def cpu_baseline(budget_s: float) -> dict:
-    """FP64 oracle on a 64^3 version of the same workload, as many steps as fit
-    the time budget (first step excluded)."""
-    from oracle import oracle
+def make_workload(name: str, n: int, storage: str, collision: str):
     from paper_2506_17713_amd import inputs
 
-    n = 64
-    w, solid, rho = inputs.sessile_3d(n=n, r=15, w=5, storage="F64", wet_mode="PHI", wet=1.1)
+    if name == "sessile":
+        r = max(15, 30 * n // 256)  # 30 at 256^3 (the configuration), 15 on the small oracle sample
+        w, solid, rho = inputs.sessile_3d(n=n, r=float(r), storage=storage, collision=collision,
+                                          wet_mode="PHI", wet=1.1)
+        desc = f"sessile droplet D3Q19 {collision} Shan-Chen CS T=0.8Tc {n}^3 r={r} wall z=0 phi=1.1"
+    elif name == "droplet2d":
+        w, solid, rho = inputs.droplet_2d(n=n, storage=storage, collision=collision)
+        desc = f"droplet D2Q9 {collision} Shan-Chen CS T=0.7Tc {n}^2 r=20 periodic"
+    else:
+        w, solid, rho = inputs.two_component_pack(n=n, storage=storage)
+        desc = (f"two-component Shan-Chen D3Q19 {w.collision} sphere pack {n}^3 radii 8-16 porosity 0.35, "
+                f"body force 1e-6")
+    return w, solid, rho, desc
+
+
+def cpu_baseline(budget_s: float, name: str) -> dict:
+    """FP64 oracle on a small version of the same workload (64^3 sessile,
+    full 128^2 droplet, 48^3 two-component pack), as many steps as fit the
+    time budget (first step excluded)."""
+    from oracle import oracle
+
+    n = {"sessile": 64, "droplet2d": 128, "pack2": 48}[name]
+    w, solid, rho, desc = make_workload(name, n, "F64", "BGK" if name == "droplet2d" else "MRT")
+    if name == "pack2":
+        w = w.with_(collision="BGK")
     st = oracle.State(w, solid, rho)
     st.step(1)
     t0 = time.perf_counter()
@@ -94,8 +123,7 @@ def cpu_baseline(budget_s: float) -> dict:
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": w.nc * w.N * k / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"sessile droplet D3Q19 MRT CS T=0.8Tc at 64^3 (r=15), {k} steps FP64, "
-                      f"{dt:.1f} s"}
+            "sample": f"{desc}, {k} steps FP64, {dt:.1f} s"}
 
 
 def main():
@@ -109,9 +137,10 @@ def main():
 
     from paper_2506_17713_amd import inputs, lbm
 
-    n = args.n
-    w, solid, rho = inputs.sessile_3d(n=n, storage=args.storage, collision=args.collision,
-                                      wet_mode="PHI", wet=1.1)
+    n = args.n or {"sessile": 256, "droplet2d": 128, "pack2": 400}[args.workload]
+    storage = args.storage if args.workload != "droplet2d" or args.storage != "F32" else "F64"
+    collision = "BGK" if args.workload != "sessile" else args.collision
+    w, solid, rho, desc = make_workload(args.workload, n, storage, collision)
     sol = lbm.Solver(w, solid, rho, device="cuda:0")
     stream = sol.stream
     print(f"# init done {w.shape} {w.storage} {w.collision}", file=sys.stderr, flush=True)
@@ -134,13 +163,14 @@ def main():
     achieved = b_alg / (ms_step * 1e-3) / 1e9
     print(f"# {args.steps} steps: {ms:.2f} ms (events), wall {wall:.3f} s, mass {stats['mass'][0]:.6e}, "
           f"nonfinite {stats['nonfinite']}", file=sys.stderr, flush=True)
-    traffic = measured_traffic(w)
+    traffic = measured_traffic(w, args.workload)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_seconds)
-    dtype = {"F32": "f32", "F64": "f64", "F16DEV": "f16dev+f32", "BF16DEV": "bf16dev+f32"}[args.storage]
+        cpu = cpu_baseline(args.cpu_seconds, args.workload)
+    dtype = {"F32": "f32", "F64": "f64", "F16DEV": "f16dev+f32", "BF16DEV": "bf16dev+f32"}[w.storage]
+    lat = "D2Q9" if args.workload == "droplet2d" else "D3Q19"
     line = {
-        "metric": "MLUPS of fused D3Q19 Shan-Chen step (% HBM roofline)",
+        "metric": f"MLUPS of fused {lat} Shan-Chen step (% HBM roofline)",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -152,8 +182,7 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"sessile droplet D3Q19 {w.collision} Shan-Chen CS T=0.8Tc {n}^3 "
-                               f"r=30 wall z=0 phi=1.1", "nodes": w.N, "components": w.nc,
+        "config": {"workload": desc, "nodes": w.N, "components": w.nc,
                    "storage": w.storage, "fluid_nodes": int((solid == 0).sum())},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -61,7 +61,8 @@ enum { LBM_WET_PHI = 0, LBM_WET_DRHO = 1 };
 
 typedef struct lbm_params {
     int32_t lattice;            /* LBM_D2Q9 or LBM_D3Q19                       */
-    int32_t nx, ny, nz;         /* lattice extent; nz = 1 for D2Q9             */
+    int32_t nx, ny, nz;         /* lattice extent; nz = 1 for D2Q9; at most
+                                   2^31 - 1 nodes and nx*ny < 2^29 (3-D)       */
     int32_t n_comp;             /* 1 or 2 fluid components                     */
     int32_t collision;          /* LBM_BGK or LBM_MRT                          */
     int32_t storage;            /* LBM_STORE_*                                 */

@@ -37,6 +37,8 @@ int validate(const lbm_params* p) {
     if (p->lattice == LBM_D2Q9 && p->nz != 1) return LBM_ERR_ARG;
     const long long N = (long long)p->nx * p->ny * p->nz;
     if (N >= (1LL << 31)) return LBM_ERR_ARG;
+    // in-plane byte offsets are 32-bit (8-byte values at most)
+    if ((long long)p->nx * (p->lattice == LBM_D2Q9 ? 1 : p->ny) >= (1LL << 29)) return LBM_ERR_ARG;
     if (p->n_comp < 1 || p->n_comp > 2) return LBM_ERR_ARG;
     if (p->collision != LBM_BGK && p->collision != LBM_MRT) return LBM_ERR_ARG;
     if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_BF16DEV) return LBM_ERR_ARG;
@@ -435,6 +437,8 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     h->since_check = 0;
     h->have_prev = false;
     h->wet_uniform = wet == nullptr;
+    // LBM_CHUNK (environment, tuning only): planes per workgroup along the
+    // marching axis; unset or 0 chooses about 2048 workgroups per launch.
     const char* ch = std::getenv("LBM_CHUNK");
     h->chunk_override = ch ? std::atoi(ch) : 0;
 

@@ -655,13 +655,11 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
         // outer ring (halo 2, which feeds only virtual densities) without a
         // solid neighbour.
         auto need = [&](int j) { return h_on[j] && !(wh[j] & 1u) && !(h_outer[j] && wh[j] == 0u); };
-        // With plain storage and BGK all loads of the plane are issued before
-        // any is waited for, so the halo pulls do not add a second memory
-        // latency.  MRT (whose collision needs more registers) and deviation
-        // storage (which also loads rho* per direction) keep the sequential
-        // order: with two nodes in flight they no longer fit three waves per
-        // SIMD without spilling, which costs more than the latency saved.
-        constexpr bool OVERLAP = !SS::DEV && COLL == COLL_BGK;
+        // With plain storage all loads of the plane are issued before any is
+        // waited for, so the halo pulls do not add a second memory latency.
+        // Deviation storage (which also loads rho* per direction) keeps the
+        // sequential order to bound register use.
+        constexpr bool OVERLAP = !SS::DEV;
         Pull<LAT, ST, NC> po;
         Pull<LAT, ST, NC> ph[OVERLAP ? HPT : 1];
         po.issue(P, own_a, own_b, c, wo);

@@ -99,6 +99,7 @@ def test_workspace_size_and_validation(lib):
     p = _params(lattice="D2Q9"); bad.append(p)               # nz != 1 for D2Q9
     p = _params(); p.eos_T[0] = 1.0; bad.append(p)           # psi argument > 0 inside the bounds
     p = _params(collision="MRT"); p.mrt_s[0][9] = 2.5; bad.append(p)
+    p = _params(); p.nx, p.ny, p.nz = 1 << 15, 1 << 14, 1; bad.append(p)  # plane of 2^29 nodes
     for p in bad:
         assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -1
 
