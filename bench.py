@@ -35,13 +35,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 500; 1000 for adjoint)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=None, help="lattice size (default: 256, 128 for droplet2d, "
                                                          "400 for pack2)")
-    ap.add_argument("--workload", default="sessile", choices=["sessile", "droplet2d", "pack2"],
+    ap.add_argument("--workload", default="sessile", choices=["sessile", "droplet2d", "pack2", "adjoint"],
                     help="sessile: D3Q19 MRT sessile droplet (the headline line); droplet2d: D2Q9 BGK FP64 "
-                         "droplet; pack2: D3Q19 two-component sphere pack")
+                         "droplet; pack2: D3Q19 two-component sphere pack; adjoint: gradient of the "
+                         "saturation over 1000 steps of the 128^3 pack (checkpoint every 100)")
     ap.add_argument("--storage", default="F32", choices=["F32", "F64", "F16DEV", "BF16DEV"])
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -126,8 +127,55 @@ def cpu_baseline(budget_s: float, name: str) -> dict:
             "sample": f"{desc}, {k} steps FP64, {dt:.1f} s"}
 
 
+def run_adjoint(args) -> dict:
+    """Gradient of the smooth non-wetting saturation after `steps` (default
+    1000) FP32 steps of the 128^3 single-component pack (porosity 0.4, CS at
+    T_r = 0.8, MRT) with respect to the per-voxel wetting parameter and T_r,
+    with a checkpoint every 100 steps: the forward run stores checkpoints,
+    then each segment is recomputed and back-propagated."""
+    import torch
+
+    from paper_2506_17713_amd import inputs, lbm
+
+    steps = args.steps
+    w, solid, rho = inputs.adjoint_pack(n=args.n or 128, storage="F32")
+    rho_mid = 0.5 * (w.rho_min[0] + w.rho_max[0])
+    delta = 0.05 * (w.rho_max[0] - w.rho_min[0])
+    sol = lbm.Solver(w, solid, rho, device="cuda:0")
+    sol.step(args.warmup)  # forward warm-up of the kernels (the gradient starts after it)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(sol.stream)
+    sol.step(100)
+    ev1.record(sol.stream)
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1) / 100
+    t0 = time.perf_counter()
+    L, dwet, dT = sol.grad(steps, 100, "saturation", rho_mid, delta)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    sol.close()
+    # forward 'steps' (checkpoints) + recompute 'steps' + reverse 'steps'
+    rev_ms = (secs * 1e3 - 2 * steps * fwd_ms) / steps
+    return {
+        "metric": "MLUPS of the reverse-mode gradient through the fused D3Q19 step (forward, recompute "
+                  "and adjoint per step)",
+        "value": round(w.N * steps / secs / 1e6, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(secs * 1e3 / steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"adjoint: CS T=0.8Tc MRT 128^3 sphere pack porosity 0.4 radii 6-14, {steps} "
+                               f"steps, checkpoint every 100, dS/d(wet) and dS/dT_r",
+                   "nodes": w.N, "components": 1, "storage": "F32", "fluid_nodes": int((solid == 0).sum()),
+                   "grad_seconds": round(secs, 3), "forward_ms_per_step": round(fwd_ms, 4),
+                   "reverse_ms_per_step_est": round(rev_ms, 4), "S": L, "dS_dTr": dT},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
+    if args.steps is None:
+        args.steps = 1000 if args.workload == "adjoint" else 500
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU x-slab sharding is "
                                    "described in DESIGN.md and not implemented", "n_gpus": args.gpus}))
@@ -137,6 +185,9 @@ def main():
 
     from paper_2506_17713_amd import inputs, lbm
 
+    if args.workload == "adjoint":
+        print(json.dumps(run_adjoint(args)), flush=True)
+        return
     n = args.n or {"sessile": 256, "droplet2d": 128, "pack2": 400}[args.workload]
     storage = args.storage if args.workload != "droplet2d" or args.storage != "F32" else "F64"
     collision = "BGK" if args.workload != "sessile" else args.collision
