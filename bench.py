@@ -234,7 +234,8 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": desc, "nodes": w.N, "components": w.nc,
-                   "storage": w.storage, "fluid_nodes": int((solid == 0).sum())},
+                   "storage": w.storage, "fluid_nodes": int((solid == 0).sum()),
+                   "fluid_MLUPS": round(w.nc * int((solid == 0).sum()) * args.steps / (ms * 1e-3) / 1e6, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": b_alg, "kernel": "k_step (fused step)"},

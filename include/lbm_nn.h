@@ -70,6 +70,16 @@ int lbm_nn_up_bwd(const float* dY, int c, int D, int H, int W, float* dX, void* 
  * is scratch.  dY = dL/dY (may be NULL). */
 int lbm_nn_mse(const float* Y, const float* T, const float* mask, int c, int64_t P, double* loss, float* dY,
                void* stream);
+/* Symmetry transform of a field for training-set augmentation, written by the
+ * callers that build training sets from solver output:
+ *   Y[k](r) = sign[k] * X[src[k]](g^-1 r),  X, Y device float [c][D][H][W], c <= 8,
+ * with g = periodic shift (host int shift[3] along D, H, W) o axis flips (host
+ * int flip[3], nonzero = reverse that axis) o exchange of the D and H axes when
+ * swap != 0 (needs D == H).  src/sign (host, c entries) permute and negate the
+ * channels, as vector components require.  Y must not alias X.
+ * Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
+int lbm_nn_augment(const float* X, float* Y, int c, int D, int H, int W, const int* shift, const int* flip,
+                   int swap, const int* src, const float* sign, void* stream);
 /* Adam update (Kingma & Ba) of n parameters at step t >= 1. */
 int lbm_nn_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
                 float eps, int t, void* stream);

@@ -457,12 +457,31 @@ __global__ void k_sum_fixed(const double* __restrict__ x, int n, double* __restr
     if (threadIdx.x == 0) *out = v;
 }
 
+// First pass of a fixed-order sum of n values: block b adds the values
+// [b * per, (b + 1) * per) (lane-strided, then a fixed shuffle tree and the
+// waves in order) into part[b].  k_sum_fixed over part completes the sum; the
+// result does not depend on scheduling.
+constexpr int kSumBlocks = 512;
+__global__ void __launch_bounds__(256) k_sum_partial(const double* __restrict__ x, int n, int per,
+                                                     double* __restrict__ part) {
+    __shared__ double s_w[4];
+    const int lo = blockIdx.x * per;
+    const int hi = lo + per < n ? lo + per : n;
+    double v = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) v += x[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+}
+
 // ---------------------------------------------------------------------------
 // Workspace of lbm_grad (caller-owned).
 // ---------------------------------------------------------------------------
 struct GradLayout {
     size_t ckpt, seg, lamA, lamB, fbar, Fbar, rho, rhoe, psi, U, rave, wsum, pbar, rbe, rba, flag, tacc, lpart,
-        sums, total;
+        tpart, sums, total;
     size_t state;
     int nseg, K;
 };
@@ -497,6 +516,7 @@ GradLayout grad_layout(const lbm_handle* h, const lbm_grad_req* r) {
     g.flag = take(N);
     g.tacc = take(N * 8);
     g.lpart = take(((N + 255) / 256) * 8);
+    g.tpart = take(kSumBlocks * 8);
     g.sums = take(64);
     g.total = off;
     return g;
@@ -622,9 +642,14 @@ int grad_impl(lbm_handle* h, const lbm_grad_req* r, double* L_out, double* dwet,
             lam_cur = t;
         }
     }
-    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(64), 0, st, (const double*)(gw + G.tacc), N,
-                       (double*)(gw + G.sums) + 1);
-    // k_sum_fixed strides by 64 threads over N entries: fixed order, deterministic
+    {
+        const int per = (N + kSumBlocks - 1) / kSumBlocks;
+        hipLaunchKernelGGL(k_sum_partial, dim3(kSumBlocks), dim3(256), 0, st, (const double*)(gw + G.tacc),
+                           N, per, (double*)(gw + G.tpart));
+        hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(64), 0, st, (const double*)(gw + G.tpart), kSumBlocks,
+                           (double*)(gw + G.sums) + 1);
+    }
+    // both sums use a fixed order, so the gradient is bitwise reproducible
     double sums[2];
     e = hipMemcpyAsync(sums, gw + G.sums, sizeof(sums), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -655,11 +655,13 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
         // outer ring (halo 2, which feeds only virtual densities) without a
         // solid neighbour.
         auto need = [&](int j) { return h_on[j] && !(wh[j] & 1u) && !(h_outer[j] && wh[j] == 0u); };
-        // With plain storage all loads of the plane are issued before any is
-        // waited for, so the halo pulls do not add a second memory latency.
-        // Deviation storage (which also loads rho* per direction) keeps the
-        // sequential order to bound register use.
-        constexpr bool OVERLAP = !SS::DEV;
+        // With plain storage and one component all loads of the plane are
+        // issued before any is waited for, so the halo pulls do not add a
+        // second memory latency.  Deviation storage (which also loads rho* per
+        // direction) and two components (twice the values per node) keep the
+        // sequential order: with several nodes in flight they lose a wave per
+        // SIMD, which costs more than the latency saved.
+        constexpr bool OVERLAP = !SS::DEV && NC == 1;
         Pull<LAT, ST, NC> po;
         Pull<LAT, ST, NC> ph[OVERLAP ? HPT : 1];
         po.issue(P, own_a, own_b, c, wo);

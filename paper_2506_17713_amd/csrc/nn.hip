@@ -323,6 +323,38 @@ int wgrad_chunks(int64_t P) { return P >= 65536 ? 64 : (P >= 4096 ? 8 : 1); }
 
 }  // namespace
 
+// Symmetry transform of a field X [C][D][H][W] (training-set augmentation):
+// Y[c](r) = sign[c] * X[src[c]](g^-1 r) with g = periodic shift o axis flips o
+// optional exchange of the D and H axes (needs D == H).
+struct AugArgs {
+    int src[8];
+    float sign[8];
+    int sz, sy, sx, fz, fy, fx, swap;
+};
+__global__ void k_augment(const float* __restrict__ X, float* __restrict__ Y, int C, int D, int H, int W,
+                          AugArgs a) {
+    const int64_t P = (int64_t)D * H * W;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)C * P) return;
+    const int c = (int)(i / P);
+    const int64_t p = i % P;
+    const int x = (int)(p % W), y = (int)((p / W) % H), z = (int)(p / ((int64_t)W * H));
+    // undo the shift, then the flips, then the exchange
+    int zs = z - a.sz, ys = y - a.sy, xs = x - a.sx;
+    zs = zs < 0 ? zs + D : zs;
+    ys = ys < 0 ? ys + H : ys;
+    xs = xs < 0 ? xs + W : xs;
+    if (a.fz) zs = D - 1 - zs;
+    if (a.fy) ys = H - 1 - ys;
+    if (a.fx) xs = W - 1 - xs;
+    if (a.swap) {
+        const int t = zs;
+        zs = ys;
+        ys = t;
+    }
+    Y[i] = a.sign[c] * X[(int64_t)a.src[c] * P + ((int64_t)zs * H + ys) * W + xs];
+}
+
 extern "C" {
 
 size_t lbm_nn_packed_words(int c_out, int c_in) {
@@ -445,6 +477,35 @@ int lbm_nn_adam(float* p, const float* g, float* m, float* v, int64_t n, float l
     const float c1 = 1.0f - powf(beta1, (float)t), c2 = 1.0f - powf(beta2, (float)t);
     hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n, lr, beta1, beta2,
                        eps, c1, c2);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_augment(const float* X, float* Y, int c, int D, int H, int W, const int* shift, const int* flip,
+                   int swap, const int* src, const float* sign, void* stream) {
+    if (!X || !Y || !shift || !flip || !src || !sign || c < 1 || c > 8 || D < 1 || H < 1 || W < 1)
+        return LBM_ERR_ARG;
+    if (swap && D != H) return LBM_ERR_ARG;
+    AugArgs a{};
+    for (int k = 0; k < c; ++k) {
+        if (src[k] < 0 || src[k] >= c) return LBM_ERR_ARG;
+        a.src[k] = src[k];
+        a.sign[k] = sign[k];
+    }
+    const int dims[3] = {D, H, W};
+    int sh[3];
+    for (int d = 0; d < 3; ++d) {
+        sh[d] = shift[d] % dims[d];
+        if (sh[d] < 0) sh[d] += dims[d];
+    }
+    a.sz = sh[0];
+    a.sy = sh[1];
+    a.sx = sh[2];
+    a.fz = flip[0] != 0;
+    a.fy = flip[1] != 0;
+    a.fx = flip[2] != 0;
+    a.swap = swap != 0;
+    const int64_t n = (int64_t)c * D * H * W;
+    hipLaunchKernelGGL(k_augment, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, X, Y, c, D, H, W, a);
     return ok(hipGetLastError());
 }
 

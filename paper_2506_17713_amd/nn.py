@@ -14,7 +14,7 @@ from . import lbm
 BF16, FP32 = 0, 1
 EXPORTS = ["lbm_nn_packed_words", "lbm_nn_pack", "lbm_nn_conv", "lbm_nn_wgrad_partial_words", "lbm_nn_wgrad",
            "lbm_nn_bias_grad", "lbm_nn_relu_bwd", "lbm_nn_add", "lbm_nn_pool", "lbm_nn_pool_bwd", "lbm_nn_up",
-           "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam"]
+           "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam", "lbm_nn_augment"]
 
 _lib = None
 
@@ -40,6 +40,7 @@ def load():
         lib.lbm_nn_up_bwd.argtypes = [vp, i, i, i, i, vp, vp]
         lib.lbm_nn_mse.argtypes = [vp, vp, vp, i, i64, vp, vp, vp]
         lib.lbm_nn_adam.argtypes = [vp, vp, vp, vp, i64, f, f, f, f, i, vp]
+        lib.lbm_nn_augment.argtypes = [vp, vp, i, i, i, i, vp, vp, i, vp, vp, vp]
         for n in EXPORTS:
             if n not in ("lbm_nn_packed_words", "lbm_nn_wgrad_partial_words"):
                 getattr(lib, n).restype = C.c_int
@@ -99,6 +100,19 @@ def bias_grad(dY: torch.Tensor) -> torch.Tensor:
 
 def relu_bwd(Y: torch.Tensor, dY: torch.Tensor) -> None:
     _chk("lbm_nn_relu_bwd", load().lbm_nn_relu_bwd(_p(Y), _p(dY), dY.numel(), _s()))
+
+
+def augment(X: torch.Tensor, shift, flip, swap: bool, src, sign) -> torch.Tensor:
+    """Y[k](r) = sign[k] X[src[k]](g^-1 r) for g = shift o flips o (D, H) exchange
+    (lbm_nn_augment); X float32 [c, D, H, W] on the device."""
+    c, D, H, W = X.shape
+    Y = torch.empty_like(X)
+    sh = (C.c_int * 3)(*[int(v) for v in shift])
+    fl = (C.c_int * 3)(*[int(bool(v)) for v in flip])
+    sr = (C.c_int * c)(*[int(v) for v in src])
+    sg = (C.c_float * c)(*[float(v) for v in sign])
+    _chk("lbm_nn_augment", load().lbm_nn_augment(_p(X), _p(Y), c, D, H, W, sh, fl, int(bool(swap)), sr, sg, _s()))
+    return Y
 
 
 def add_(y: torch.Tensor, x: torch.Tensor) -> None:

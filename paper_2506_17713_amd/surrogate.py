@@ -275,23 +275,47 @@ def make_dataset(n_samples: int, size=128, seed0=0, accel=1e-5, log=print, devic
     return xs, ys, info
 
 
-def train(model: Surrogate, xs, ys, epochs: int, lr=1e-3, log=print, seed=0):
+def symmetry(rng, shape):
+    """A random symmetry of the steady problem (periodic pack, body force
+    along +x): periodic shift, axis flips and, for D == H, the exchange of the
+    z and y axes.  Returns the lbm_nn_augment arguments for the four target
+    channels (u_x, u_y, u_z, p).  The velocity maps as A u(g^-1 r) with A the
+    flips after the exchange; flipping x also reverses the forcing, and since
+    the flow is linear in the forcing (Stokes regime) every channel is then
+    negated, which keeps u_x as it is."""
+    D, H, W = shape
+    shift = [int(rng.integers(n)) for n in shape]
+    flip = [int(rng.integers(2)) for _ in range(3)]  # along (z, y, x)
+    swap = bool(D == H and rng.integers(2))
+    sz, sy, sx = (-1.0 if f else 1.0 for f in flip)
+    src = [0, 2 if swap else 1, 1 if swap else 2, 3]
+    sign = [1.0, sx * sy, sx * sz, sx]
+    return shift, flip, swap, src, sign
+
+
+def train(model: Surrogate, xs, ys, epochs: int, lr=1e-3, log=print, seed=0, augment=False):
     """xs: device masks [1, D, H, W]; ys: host float32 targets [4, D, H, W]
     (targets_of).  Each channel is normalised on the host to unit RMS over the
-    pore voxels of the whole set, then the set is uploaded once."""
+    pore voxels of the whole set, then the set is uploaded once.  With
+    augment, every sample is seen under a fresh random symmetry (symmetry())."""
     npore = sum(float(x.sum()) for x in xs)
     s2 = sum((y.astype(np.float64) ** 2).sum(axis=(1, 2, 3)) for y in ys) / npore
     model.scale = np.sqrt(np.maximum(s2, 1e-30))
     inv = (1.0 / model.scale)[:, None, None, None]
     ys_n = [torch.tensor((y * inv).astype(np.float32), device=xs[0].device) for y in ys]
-    order = np.random.default_rng(seed).permutation
+    rng = np.random.default_rng(seed)
     hist = []
     for ep in range(epochs):
         tot = 0.0
-        for i in order(len(xs)):
+        for i in rng.permutation(len(xs)):
+            x, y = xs[i], ys_n[i]
+            if augment:
+                shift, flip, swap, src, sign = symmetry(rng, tuple(x.shape[1:]))
+                x = nn.augment(x, shift, flip, swap, [0], [1.0])
+                y = nn.augment(y, shift, flip, swap, src, sign)
             tape = []
-            out = model.forward(xs[i], tape)
-            loss, dout = nn.mse(out, ys_n[i], xs[i][0])
+            out = model.forward(x, tape)
+            loss, dout = nn.mse(out, y, x[0])
             grads = model.backward(tape, dout)
             model.adam_step(grads, lr)
             tot += float(loss)

@@ -96,6 +96,7 @@ def main(argv=None):
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp32"])
     ap.add_argument("--save-model", default=None)
     ap.add_argument("--load-model", default=None)
+    ap.add_argument("--augment", action="store_true", help="train under random symmetries of the problem")
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     model = Surrogate(prec=nn.BF16 if a.prec == "bf16" else nn.FP32)
@@ -112,10 +113,10 @@ def main(argv=None):
         xs, ys, info = make_dataset(a.train, a.size, log=log)
         t_data = time.perf_counter() - t0
         t1 = time.perf_counter()
-        hist = train(model, xs, ys, a.epochs, lr=a.lr, log=log)
+        hist = train(model, xs, ys, a.epochs, lr=a.lr, log=log, augment=a.augment)
         t_train = time.perf_counter() - t1
         del xs, ys
-        summ.update({"n_train": a.train, "train_size": a.size, "epochs": a.epochs, "lr": a.lr,
+        summ.update({"n_train": a.train, "train_size": a.size, "epochs": a.epochs, "lr": a.lr, "augment": a.augment,
                      "data_seconds": t_data, "train_seconds": t_train, "train_mse": hist,
                      "train_info": info})
         if a.save_model:

@@ -226,3 +226,47 @@ def test_trained_network_gains_over_the_start_from_rest(T, ops):
     assert err_u < 0.6
     assert err_k < 0.3
     assert abs(warm["k"] - cold["k"]) < 1e-3 * cold["k"]
+
+
+@pytest.mark.parametrize("shift,flip,swap", [((1, 2, 3), (0, 0, 0), False), ((0, 5, 7), (1, 0, 1), True),
+                                             ((3, 0, 0), (0, 1, 0), True), ((0, 0, 0), (1, 1, 1), False)])
+def test_augment_kernel_matches_numpy(T, ops, shift, flip, swap):
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((4, 6, 6, 10)).astype(np.float32)
+    src, sign = [3, 0, 2, 1], [1.0, -1.0, 0.5, 2.0]
+    Y = ops.augment(T.tensor(X, device="cuda"), shift, flip, swap, src, sign).cpu().numpy()
+    # reference: exchange (z, y), then flips, then periodic shift, per output channel
+    R = X[src] * np.array(sign, dtype=np.float32)[:, None, None, None]
+    if swap:
+        R = np.swapaxes(R, 1, 2)
+    for ax, f in enumerate(flip):
+        if f:
+            R = np.flip(R, axis=1 + ax)
+    R = np.roll(R, shift=shift, axis=(1, 2, 3))
+    assert np.array_equal(Y, R)
+
+
+def test_symmetry_maps_steady_solutions_to_steady_solutions(T, ops):
+    """The channel rules of surrogate.symmetry (vector components, and the sign
+    reversal of the forcing under an x flip) are those of the solver itself:
+    the transformed steady field equals the steady field of the transformed
+    pack."""
+    from paper_2506_17713_amd import inputs
+    from paper_2506_17713_amd.surrogate import solve_steady, symmetry, targets_of
+
+    a, n = 1e-5, 24
+    solid = inputs.sphere_pack((n,) * 3, (3.0, 6.0), 0.45, seed=2)
+    tgt = targets_of(solve_steady(solid, accel=a, tol=1e-9), solid, a)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        shift, flip, swap, src, sign = symmetry(rng, solid.shape)
+        flip = [1, flip[1], flip[2]] if not any(flip) else flip
+        sz, sy, sx = (-1.0 if f else 1.0 for f in flip)
+        sign = [1.0, sx * sy, sx * sz, sx]
+        mask = T.tensor((solid == 0).astype(np.float32)[None], device="cuda")
+        m2 = ops.augment(mask, shift, flip, swap, [0], [1.0]).cpu().numpy()[0]
+        solid2 = (m2 < 0.5).astype(np.uint8)
+        t_aug = ops.augment(T.tensor(tgt, device="cuda"), shift, flip, swap, src, sign).cpu().numpy()
+        t2 = targets_of(solve_steady(solid2, accel=a, tol=1e-9), solid2, a)
+        err = np.abs(t_aug - t2).max() / np.abs(t2).max()
+        assert err < 1e-4, (shift, flip, swap, err)
