@@ -287,10 +287,15 @@ def symmetry(rng, shape):
     shift = [int(rng.integers(n)) for n in shape]
     flip = [int(rng.integers(2)) for _ in range(3)]  # along (z, y, x)
     swap = bool(D == H and rng.integers(2))
+    return symmetry_args(shift, flip, swap)
+
+
+def symmetry_args(shift, flip, swap: bool):
+    """lbm_nn_augment arguments of one symmetry (see symmetry())."""
     sz, sy, sx = (-1.0 if f else 1.0 for f in flip)
     src = [0, 2 if swap else 1, 1 if swap else 2, 3]
     sign = [1.0, sx * sy, sx * sz, sx]
-    return shift, flip, swap, src, sign
+    return list(shift), list(flip), bool(swap), src, sign
 
 
 def train(model: Surrogate, xs, ys, epochs: int, lr=1e-3, log=print, seed=0, augment=False):

@@ -247,26 +247,27 @@ def test_augment_kernel_matches_numpy(T, ops, shift, flip, swap):
 
 
 def test_symmetry_maps_steady_solutions_to_steady_solutions(T, ops):
-    """The channel rules of surrogate.symmetry (vector components, and the sign
-    reversal of the forcing under an x flip) are those of the solver itself:
+    """The channel rules of surrogate.symmetry are those of the solver itself:
     the transformed steady field equals the steady field of the transformed
-    pack."""
+    pack.  Shifts, y/z flips and the y/z exchange are exact symmetries of the
+    lattice (checked at the training forcing); an x flip also reverses the
+    forcing and relies on the flow being linear in it, which holds to O(Re):
+    it is checked at a 100 times weaker forcing."""
     from paper_2506_17713_amd import inputs
-    from paper_2506_17713_amd.surrogate import solve_steady, symmetry, targets_of
+    from paper_2506_17713_amd.surrogate import solve_steady, symmetry_args, targets_of
 
-    a, n = 1e-5, 24
+    n = 24
     solid = inputs.sphere_pack((n,) * 3, (3.0, 6.0), 0.45, seed=2)
-    tgt = targets_of(solve_steady(solid, accel=a, tol=1e-9), solid, a)
-    rng = np.random.default_rng(4)
-    for _ in range(3):
-        shift, flip, swap, src, sign = symmetry(rng, solid.shape)
-        flip = [1, flip[1], flip[2]] if not any(flip) else flip
-        sz, sy, sx = (-1.0 if f else 1.0 for f in flip)
-        sign = [1.0, sx * sy, sx * sz, sx]
-        mask = T.tensor((solid == 0).astype(np.float32)[None], device="cuda")
+    mask = T.tensor((solid == 0).astype(np.float32)[None], device="cuda")
+    cases = [(1e-5, (17, 22, 21), (1, 1, 0), True, 1e-6), (1e-5, (3, 0, 9), (0, 1, 0), False, 1e-6),
+             (1e-7, (5, 11, 2), (1, 1, 1), True, 1e-4), (1e-7, (0, 4, 0), (0, 0, 1), False, 1e-4)]
+    for a, shift, flip, swap, tol in cases:
+        tgt = targets_of(solve_steady(solid, accel=a, tol=1e-10), solid, a)
+        shift, flip, swap, src, sign = symmetry_args(shift, flip, swap)
         m2 = ops.augment(mask, shift, flip, swap, [0], [1.0]).cpu().numpy()[0]
         solid2 = (m2 < 0.5).astype(np.uint8)
         t_aug = ops.augment(T.tensor(tgt, device="cuda"), shift, flip, swap, src, sign).cpu().numpy()
-        t2 = targets_of(solve_steady(solid2, accel=a, tol=1e-9), solid2, a)
-        err = np.abs(t_aug - t2).max() / np.abs(t2).max()
-        assert err < 1e-4, (shift, flip, swap, err)
+        t2 = targets_of(solve_steady(solid2, accel=a, tol=1e-10), solid2, a)
+        err = float(np.abs(t_aug.astype(np.float64) - t2).max() / np.abs(t2).max())
+        print(f"symmetry a={a} shift={shift} flip={flip} swap={swap}: {err:.2e}")
+        assert err < tol, (a, shift, flip, swap, err)
