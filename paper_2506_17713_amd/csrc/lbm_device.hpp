@@ -507,14 +507,24 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
 // ---------------------------------------------------------------------------
 // The fused step (MOM = false) or the moment evaluation (MOM = true).
 // ---------------------------------------------------------------------------
-// Minimum waves per SIMD the register allocator must allow (1: no bound;
-// the one-component single-precision kernels fit three waves by themselves).
+// Minimum waves per SIMD the register allocator must allow.  1 (no bound)
+// in general: the one-component FP32 kernels fit three waves by themselves,
+// and two components or FP64 would spill.  The one-component deviation
+// storage kernels are held to three (MRT otherwise takes 171 registers and
+// runs two waves; with the bound it spills two and runs 9 % faster).
 #ifndef LBM_WAVES_PER_EU
 #define LBM_WAVES_PER_EU 1
 #endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 0
+#endif
+#ifndef LBM_DEV_WAVES_PER_EU
+#define LBM_DEV_WAVES_PER_EU 3
+#endif
 
 template <int LAT, int NC, int ST, int COLL, bool MOM, int TA, int TB, bool CARRY>
-__global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+__global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu((ST == ST_F16 || ST == ST_BF16) && NC == 1 ? LBM_DEV_WAVES_PER_EU
+                                                                                  : LBM_WAVES_PER_EU)))
     k_step(StepArgs<typename Store<ST>::R> P) {
     using L = Lat<LAT>;
     using SS = Store<ST>;
@@ -1059,7 +1069,11 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(LBM
                     using T = decltype(val);
                     auto bp = (__attribute__((address_space(1))) char*)(base + off);
                     asm volatile("" : "+s"(bp));
+#if LBM_NT_STORE
+                    __builtin_nontemporal_store(val, (__attribute__((address_space(1))) T*)(bp + e * (uint32_t)sizeof(T)));
+#else
                     *(__attribute__((address_space(1))) T*)(bp + e * (uint32_t)sizeof(T)) = val;
+#endif
                 };
                 if constexpr (SS::DEV) {
                     st(reinterpret_cast<char*>(P.rout), ((size_t)k * Ns + pl) * 4, (float)r);

@@ -17,9 +17,10 @@
    cold run at r < 1e-6.  Warm seconds include inference, the download of the
    prediction and the upload of the initial state.
 
---save-model / --load-model split training and evaluation over runs (with
---train > 0 a loaded model is trained further); --test-first selects the
-first held-out seed offset.
+--save-model / --load-model split training and evaluation over runs.  A
+loaded model is only evaluated unless --train is given explicitly (then it is
+trained further, with fresh Adam moments); --test-first selects the first
+held-out seed offset.
 """
 from __future__ import annotations
 
@@ -83,9 +84,10 @@ def summarise(res: list) -> dict:
             "warm_faster_k_rule": int(sum(r["warm_k_s"] < r["cold_k_s"] for r in res))}
 
 
-def main(argv=None):
+def parse_args(argv=None) -> argparse.Namespace:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=256)
+    ap.add_argument("--train", type=int, default=None,
+                    help="training packs (default 256, or 0 with --load-model)")
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -98,6 +100,13 @@ def main(argv=None):
     ap.add_argument("--load-model", default=None)
     ap.add_argument("--augment", action="store_true", help="train under random symmetries of the problem")
     a = ap.parse_args(argv)
+    if a.train is None:
+        a.train = 0 if a.load_model else 256
+    return a
+
+
+def main(argv=None):
+    a = parse_args(argv)
     log = lambda m: print(m, flush=True)
     model = Surrogate(prec=nn.BF16 if a.prec == "bf16" else nn.FP32)
     log(f"surrogate parameters: {model.n_params()}")

@@ -128,3 +128,10 @@ def test_strerror(lib):
     assert lib.lbm_strerror(0) == b"ok"
     assert b"workspace" in lib.lbm_strerror(-5)
     assert lib.lbm_strerror(-99) == b"unknown error"
+
+
+def test_warm_start_driver_evaluates_a_loaded_model_without_training_it():
+    from paper_2506_17713_amd import warmstart
+    assert warmstart.parse_args([]).train == 256
+    assert warmstart.parse_args(["--load-model", "m.npz"]).train == 0
+    assert warmstart.parse_args(["--load-model", "m.npz", "--train", "64"]).train == 64
