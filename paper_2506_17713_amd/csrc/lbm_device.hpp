@@ -507,24 +507,28 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
 // ---------------------------------------------------------------------------
 // The fused step (MOM = false) or the moment evaluation (MOM = true).
 // ---------------------------------------------------------------------------
-// Minimum waves per SIMD the register allocator must allow.  1 (no bound)
-// in general: the one-component FP32 kernels fit three waves by themselves,
-// and two components or FP64 would spill.  The one-component deviation
-// storage kernels are held to three (MRT otherwise takes 171 registers and
-// runs two waves; with the bound it spills two and runs 9 % faster).
-#ifndef LBM_WAVES_PER_EU
-#define LBM_WAVES_PER_EU 1
-#endif
+// Post-collision populations are stored nontemporal: they are read again only
+// in the next step, after the whole lattice has passed through L2, so caching
+// them would only evict the current plane's halo rows (3-4 % faster steps).
 #ifndef LBM_NT_STORE
-#define LBM_NT_STORE 0
+#define LBM_NT_STORE 1
 #endif
-#ifndef LBM_DEV_WAVES_PER_EU
-#define LBM_DEV_WAVES_PER_EU 3
+// Minimum waves per SIMD the register allocator must allow (1: no bound).
+// The one-component FP32 kernels fit three waves by themselves and FP64 would
+// spill.  The one-component deviation-storage kernels are held to three (MRT
+// otherwise takes 171 registers and runs two waves; bounded, it spills two
+// and runs 9 % faster).  Bounds on the two-component kernels (three waves for
+// deviation storage, four for FP32) measured 16 % slower and no faster.
+#ifndef LBM_WAVES_1C_DEV
+#define LBM_WAVES_1C_DEV 3
 #endif
+template <int NC, int ST>
+constexpr int waves_bound() {
+    return (ST == ST_F16 || ST == ST_BF16) && NC == 1 ? LBM_WAVES_1C_DEV : 1;
+}
 
 template <int LAT, int NC, int ST, int COLL, bool MOM, int TA, int TB, bool CARRY>
-__global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu((ST == ST_F16 || ST == ST_BF16) && NC == 1 ? LBM_DEV_WAVES_PER_EU
-                                                                                  : LBM_WAVES_PER_EU)))
+__global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(waves_bound<NC, ST>())))
     k_step(StepArgs<typename Store<ST>::R> P) {
     using L = Lat<LAT>;
     using SS = Store<ST>;
