@@ -156,6 +156,17 @@ int lbm_stats(lbm_handle* h, lbm_stats_t* out);
 /* Synchronise the stream; report a latched check failure or HIP error. */
 int lbm_sync(lbm_handle* h);
 
+/* Restart from f = f^eq(rho0, u0) (Eq. 3 with the moments given), as
+ * lbm_init does, but from device arrays: for callers whose initial fields
+ * are computed on the GPU (a learned warm start).  rho0_dev [n_comp][N] and
+ * u0_dev [3][N] (NULL: rest) are device arrays of the compute type (double
+ * for LBM_STORE_F64, float otherwise), node order as in lbm_init; values at
+ * solid nodes are ignored.  Unlike lbm_init the values are not validated: a
+ * non-finite or negative density is reported by the next check.  The step
+ * counter and the residual history restart; mask, parameters and wetting
+ * field are kept.  Synchronises the stream.  Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
+int lbm_reset(lbm_handle* h, const void* rho0_dev, const void* u0_dev);
+
 /* Bytes of the raw population state (layout private to this library). */
 int lbm_state_bytes(const lbm_handle* h, size_t* bytes_out);
 /* Copy the raw state to / from a device buffer of lbm_state_bytes bytes

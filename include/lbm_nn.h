@@ -80,6 +80,19 @@ int lbm_nn_mse(const float* Y, const float* T, const float* mask, int c, int64_t
  * Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
 int lbm_nn_augment(const float* X, float* Y, int c, int D, int H, int W, const int* shift, const int* flip,
                    int swap, const int* src, const float* sign, void* stream);
+/* Initial fields of a warm-started flow solve from the network output, for
+ * the callers that start lbm_reset from a prediction.  With Y device float
+ * [4][P] (u_x, u_y, u_z, pressure channel), mask device float [P] (nonzero at
+ * pore voxels), c host double[4] and <Y3> the pore mean of channel 3:
+ *   pore voxels:  rho0[p] = 1 + c[3] (Y[3][p] - <Y3>),
+ *                 u0[d][p] = c[d] Y[d][p] - (d == 0 ? shift_x : 0)
+ *   solid voxels: rho0[p] = 1, u0[d][p] = 0
+ * rho0 [P] and u0 [3][P] are device arrays of double (real_bytes 8) or float
+ * (real_bytes 4), evaluated in double precision; the pore mean is summed in a
+ * fixed order.  scratch: device double[2 + 512] (scratch[0] = sum over pores
+ * of Y3, scratch[1] = pore count).  Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
+int lbm_nn_warm_fields(const float* Y, const float* mask, int64_t P, const double* c, double shift_x,
+                       int real_bytes, void* rho0, void* u0, double* scratch, void* stream);
 /* Adam update (Kingma & Ba) of n parameters at step t >= 1. */
 int lbm_nn_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
                 float eps, int t, void* stream);

@@ -316,6 +316,62 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Warm-start fields from a network output (lbm_nn_warm_fields): the pore
+// mean of channel 3 by per-block partial sums in a fixed order, then one
+// elementwise pass in double precision.
+__global__ void k_pore_sum_partial(const float* __restrict__ X, const float* __restrict__ mask, int64_t P,
+                                   double* __restrict__ part) {
+    double s = 0.0, m = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < P; p += (int64_t)gridDim.x * 256) {
+        const double mk = mask[p];
+        m += mk;
+        s += mk * (double)X[p];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        m += __shfl_xor(m, o, 64);
+    }
+    __shared__ double sh[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = s;
+        sh[1][threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+        part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    }
+}
+
+__global__ void k_pore_sum_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0, m = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        s += part[2 * b];
+        m += part[2 * b + 1];
+    }
+    out[0] = s;
+    out[1] = m;
+}
+
+struct WarmArgs {
+    double c[4];
+    double shift_x;
+};
+
+template <typename R>
+__global__ void k_warm_fields(const float* __restrict__ Y, const float* __restrict__ mask, int64_t P, WarmArgs a,
+                              const double* __restrict__ sums, R* __restrict__ rho0, R* __restrict__ u0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const bool pore = mask[i] != 0.0f;
+    const double mean_p = sums[1] > 0.0 ? sums[0] / sums[1] : 0.0;
+    rho0[i] = pore ? (R)(1.0 + a.c[3] * ((double)Y[3 * P + i] - mean_p)) : (R)1;
+    for (int d = 0; d < 3; ++d)
+        u0[d * P + i] = pore ? (R)(a.c[d] * (double)Y[d * P + i] - (d == 0 ? a.shift_x : 0.0)) : (R)0;
+}
+
 inline int grid1(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 inline int ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_HIP; }
 
@@ -477,6 +533,26 @@ int lbm_nn_adam(float* p, const float* g, float* m, float* v, int64_t n, float l
     const float c1 = 1.0f - powf(beta1, (float)t), c2 = 1.0f - powf(beta2, (float)t);
     hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n, lr, beta1, beta2,
                        eps, c1, c2);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_warm_fields(const float* Y, const float* mask, int64_t P, const double* c, double shift_x,
+                       int real_bytes, void* rho0, void* u0, double* scratch, void* stream) {
+    if (!Y || !mask || !c || !rho0 || !u0 || !scratch || P < 1 || (real_bytes != 4 && real_bytes != 8))
+        return LBM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int nblk = 256;
+    hipLaunchKernelGGL(k_pore_sum_partial, dim3(nblk), dim3(256), 0, st, Y + 3 * P, mask, P, scratch + 2);
+    hipLaunchKernelGGL(k_pore_sum_final, dim3(1), dim3(64), 0, st, scratch + 2, nblk, scratch);
+    WarmArgs a{};
+    for (int k = 0; k < 4; ++k) a.c[k] = c[k];
+    a.shift_x = shift_x;
+    if (real_bytes == 8)
+        hipLaunchKernelGGL(k_warm_fields<double>, dim3(grid1(P)), dim3(256), 0, st, Y, mask, P, a, scratch,
+                           (double*)rho0, (double*)u0);
+    else
+        hipLaunchKernelGGL(k_warm_fields<float>, dim3(grid1(P)), dim3(256), 0, st, Y, mask, P, a, scratch,
+                           (float*)rho0, (float*)u0);
     return ok(hipGetLastError());
 }
 

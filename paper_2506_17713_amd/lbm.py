@@ -20,7 +20,7 @@ ERRORS = {-1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP", -4: "
           -5: "LBM_ERR_SPACE"}
 STORAGE = {"F64": 0, "F32": 1, "F16DEV": 2, "BF16DEV": 3}
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_moments", "lbm_stats", "lbm_sync",
-           "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_grad_workspace_size", "lbm_grad",
+           "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_reset", "lbm_grad_workspace_size", "lbm_grad",
            "lbm_free", "lbm_strerror"]
 OBSERVABLES = {"saturation": 0, "drho": 1}
 
@@ -86,6 +86,7 @@ def load():
         lib.lbm_state_bytes.argtypes = [vp, C.POINTER(sz)]
         lib.lbm_get_state.argtypes = [vp, vp]
         lib.lbm_set_state.argtypes = [vp, vp]
+        lib.lbm_reset.argtypes = [vp, vp, vp]
         lib.lbm_grad_workspace_size.argtypes = [vp, vp, C.POINTER(sz)]
         lib.lbm_grad.argtypes = [vp, vp, C.POINTER(C.c_double), vp, C.POINTER(C.c_double)]
         lib.lbm_free.argtypes = [vp]
@@ -209,6 +210,15 @@ class Solver:
     def set_state(self, buf) -> None:
         assert buf.numel() == self.state_bytes()
         _check("lbm_set_state", self.lib.lbm_set_state(self.h, buf.data_ptr()))
+
+    def reset(self, rho0, u0=None) -> None:
+        """Restart from f^eq of device fields (lbm_reset): rho0 [n_comp, N] and
+        u0 [3, N] (None: rest), contiguous device tensors of the compute type."""
+        N = self.w.N
+        assert rho0.dtype == self.real and rho0.is_cuda and rho0.is_contiguous() and rho0.numel() == self.w.nc * N
+        if u0 is not None:
+            assert u0.dtype == self.real and u0.is_cuda and u0.is_contiguous() and u0.numel() == 3 * N
+        _check("lbm_reset", self.lib.lbm_reset(self.h, rho0.data_ptr(), None if u0 is None else u0.data_ptr()))
 
     def grad(self, nsteps: int, ckpt_every: int, observable: str = "saturation", rho_mid: float = 0.0,
              delta: float = 1.0, dL_drho=None):

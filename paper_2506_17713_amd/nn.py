@@ -14,7 +14,7 @@ from . import lbm
 BF16, FP32 = 0, 1
 EXPORTS = ["lbm_nn_packed_words", "lbm_nn_pack", "lbm_nn_conv", "lbm_nn_wgrad_partial_words", "lbm_nn_wgrad",
            "lbm_nn_bias_grad", "lbm_nn_relu_bwd", "lbm_nn_add", "lbm_nn_pool", "lbm_nn_pool_bwd", "lbm_nn_up",
-           "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam", "lbm_nn_augment"]
+           "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam", "lbm_nn_augment", "lbm_nn_warm_fields"]
 
 _lib = None
 
@@ -41,6 +41,7 @@ def load():
         lib.lbm_nn_mse.argtypes = [vp, vp, vp, i, i64, vp, vp, vp]
         lib.lbm_nn_adam.argtypes = [vp, vp, vp, vp, i64, f, f, f, f, i, vp]
         lib.lbm_nn_augment.argtypes = [vp, vp, i, i, i, i, vp, vp, i, vp, vp, vp]
+        lib.lbm_nn_warm_fields.argtypes = [vp, vp, i64, vp, C.c_double, i, vp, vp, vp, vp]
         for n in EXPORTS:
             if n not in ("lbm_nn_packed_words", "lbm_nn_wgrad_partial_words"):
                 getattr(lib, n).restype = C.c_int
@@ -113,6 +114,20 @@ def augment(X: torch.Tensor, shift, flip, swap: bool, src, sign) -> torch.Tensor
     sg = (C.c_float * c)(*[float(v) for v in sign])
     _chk("lbm_nn_augment", load().lbm_nn_augment(_p(X), _p(Y), c, D, H, W, sh, fl, int(bool(swap)), sr, sg, _s()))
     return Y
+
+
+def warm_fields(Y: torch.Tensor, mask: torch.Tensor, c, shift_x: float, dtype=torch.float64):
+    """Solver start (rho0 [1, P], u0 [3, P]) of the given dtype from the
+    network output Y float32 [4, ...] (lbm_nn_warm_fields)."""
+    P = Y[0].numel()
+    rho0 = torch.empty((1, P), dtype=dtype, device=Y.device)
+    u0 = torch.empty((3, P), dtype=dtype, device=Y.device)
+    scratch = torch.empty(2 + 512, dtype=torch.float64, device=Y.device)
+    cc = (C.c_double * 4)(*[float(v) for v in c])
+    _chk("lbm_nn_warm_fields", load().lbm_nn_warm_fields(_p(Y), _p(mask), P, cc, float(shift_x),
+                                                         8 if dtype == torch.float64 else 4, _p(rho0), _p(u0),
+                                                         _p(scratch), _s()))
+    return rho0, u0
 
 
 def add_(y: torch.Tensor, x: torch.Tensor) -> None:

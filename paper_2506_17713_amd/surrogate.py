@@ -52,6 +52,7 @@ class Surrogate:
                 d[name] = (torch.zeros_like(self.W[name]), torch.zeros_like(self.b[name]))
         self.t = 0
         self.scale = np.ones(OUT_CH)  # per-channel target normalisation
+        self.flow_gain = 1.0  # velocity calibration (calibrate_flow)
         self.repack()
 
     def n_params(self) -> int:
@@ -159,16 +160,18 @@ class Surrogate:
         """Steady fields on the host, float64 [4, D, H, W], zero in solids:
         u nu / a (channels 0-2) and (rho - 1) c_s^2 / a (channel 3)."""
         out = self.forward(mask)
-        return out.cpu().numpy().astype(np.float64) * self.scale[:, None, None, None] * mask.cpu().numpy()
+        gain = np.array([self.flow_gain] * 3 + [1.0])
+        return out.cpu().numpy().astype(np.float64) * (self.scale * gain)[:, None, None, None] * mask.cpu().numpy()
 
     def state(self) -> dict:
-        return {"scale": self.scale, "t": self.t,
+        return {"scale": self.scale, "t": self.t, "flow_gain": self.flow_gain,
                 **{f"W_{n}": self.W[n].cpu().numpy() for n, _, _ in ARCH},
                 **{f"b_{n}": self.b[n].cpu().numpy() for n, _, _ in ARCH}}
 
     def load_state(self, st: dict) -> None:
         self.scale = np.asarray(st["scale"], dtype=np.float64)
         self.t = int(st["t"])
+        self.flow_gain = float(st["flow_gain"]) if "flow_gain" in st else 1.0
         for n, _, _ in ARCH:
             self.W[n].copy_(torch.as_tensor(np.asarray(st[f"W_{n}"]), dtype=torch.float32))
             self.b[n].copy_(torch.as_tensor(np.asarray(st[f"b_{n}"]), dtype=torch.float32))
@@ -184,7 +187,8 @@ NU = (1.0 - 0.5) / 3.0  # BGK tau = 1
 def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, rho0=None, tol=1e-6, check=100, max_steps=100000,
                  device="cuda", storage="F64", k_tol=1e-4):
     """Run single-phase flow (BGK tau = 1, body acceleration along x) from
-    f^eq(rho0, u0) (rest at rho = 1 by default) until the residual
+    f^eq(rho0, u0) (rest at rho = 1 by default; host arrays, or device
+    tensors of the compute type as from warm_start_device) until the residual
     sum|u_x(t) - u_x(t-100)| / sum|u_x| < tol.  FP64 populations by default:
     with u ~ 1e-4 the FP32 rounding noise of the velocity alone keeps this
     residual near 3e-5.
@@ -195,12 +199,15 @@ def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, rho0=None, tol=1e-6, ch
     Returns dict(u [3, N] and rho [N] torch tensors, steps, seconds, k,
     residual, k_steps, k_seconds, k_at_k_steps, history)."""
     w, solid, rho = inputs.single_phase_pack(shape=solid.shape, solid=solid, accel=accel, storage=storage)
-    if rho0 is not None:
+    on_device = isinstance(rho0, torch.Tensor)
+    if rho0 is not None and not on_device:
         rho = np.asarray(rho0, dtype=np.float64).reshape(rho.shape)
     porosity = float((solid == 0).mean())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sol = lbm.Solver(w, solid, rho, u0=u0, device=device)
+    sol = lbm.Solver(w, solid, rho, u0=None if on_device else u0, device=device)
+    if on_device:
+        sol.reset(rho0, u0)
     sol.stats()  # first reduction sets the reference velocity
     steps, res, calm = 0, 1.0, 0
     hist, k_prev, k_hit = [], None, None
@@ -257,6 +264,16 @@ def warm_fields(pred: np.ndarray, solid: np.ndarray, accel: float):
     return rho[None], u
 
 
+def warm_start_device(model: Surrogate, mask: torch.Tensor, accel: float, dtype=torch.float64):
+    """The start of warm_fields(model.predict(mask), ...) computed on the GPU
+    from the network output (lbm_nn_warm_fields): device (rho0 [1, N],
+    u0 [3, N]) of the solver's compute type, for solve_steady / Solver.reset."""
+    out = model.forward(mask)
+    g = model.flow_gain
+    c = [float(model.scale[d]) * g * accel / NU for d in range(3)] + [3.0 * accel * float(model.scale[3])]
+    return nn.warm_fields(out, mask[0], c, 0.5 * accel, dtype)
+
+
 def make_dataset(n_samples: int, size=128, seed0=0, accel=1e-5, log=print, device="cuda",
                  radii=(6.0, 14.0)):
     """Seeded packs (porosity U(0.3, 0.5)) and their steady fields (targets_of)."""
@@ -273,6 +290,22 @@ def make_dataset(n_samples: int, size=128, seed0=0, accel=1e-5, log=print, devic
         log(f"sample {s}: porosity {info[-1]['porosity']:.3f} steps {r['steps']} k {r['k']:.4f} "
             f"({r['seconds']:.1f} s)")
     return xs, ys, info
+
+
+def calibrate_flow(model: Surrogate, xs, ys) -> float:
+    """Set model.flow_gain, the one factor on the predicted velocity that best
+    reproduces the permeabilities of the given samples (least squares over
+    k_i = <u_x nu / a>_V; targets as from targets_of), and return it.
+
+    The masked MSE of training weighs the field voxel by voxel and leaves the
+    volume mean, which is k, loosely pinned: trained models carry a common k
+    bias of 10-20 % of either sign, the same on their training packs as on
+    held-out ones, with a few percent scatter around it."""
+    model.flow_gain = 1.0
+    kp = np.array([model.predict(x)[0].mean() for x in xs])
+    kt = np.array([float(np.asarray(y[0], dtype=np.float64).mean()) for y in ys])
+    model.flow_gain = float((kp * kt).sum() / (kp * kp).sum())
+    return model.flow_gain
 
 
 def symmetry(rng, shape):

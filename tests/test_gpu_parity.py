@@ -134,10 +134,13 @@ def test_sessile_3d_mrt_f32(oracle_mod):
     assert_tol(out, 1e-4)
 
 
-def test_sessile_3d_f32_ragged_drho(oracle_mod):
+@pytest.mark.parametrize("collision", ["MRT", "BGK"])
+def test_sessile_3d_f32_ragged_drho(oracle_mod, collision):
+    # 37 x 45 planes: the last tile row and the only tile column wrap (64 x 4
+    # tiles for MRT, 64 x 8 for BGK)
     shape = (29, 37, 45)
     c = inputs.load_coexistence()["CS"]["0.8"]
-    w = inputs.Workload("sessile3d", "D3Q19", shape, collision="MRT", storage="F32",
+    w = inputs.Workload("sessile3d", "D3Q19", shape, collision=collision, storage="F32",
                         eos_T=(c["T"],) * 2, A=(c["A"],) * 2, wet_mode=("DRHO", "DRHO"),
                         wet=(0.02, 0.02), rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2)
     solid = inputs.walls(shape, "z", (0, 28))
@@ -241,6 +244,32 @@ def test_bitwise_determinism_and_resume():
     assert torch.equal(ra, rc_) and torch.equal(ua, uc)
     sa, sb = a.stats(), b.stats()
     assert sa["mass"] == sb["mass"] and sa["momentum"] == sb["momentum"]
+
+
+@pytest.mark.parametrize("storage", ["F64", "F32", "F16DEV"])
+def test_reset_from_device_fields_matches_init(storage):
+    """lbm_reset from device arrays gives the state lbm_init gives from the
+    same values on the host, and the same trajectory after it."""
+    import torch
+
+    from paper_2506_17713_amd import lbm
+
+    w, solid, rho = inputs.sessile_3d(n=24, r=6, w=3, storage=storage)
+    rng = np.random.default_rng(3)
+    rho = rho * (1.0 + 0.01 * rng.standard_normal(rho.shape))
+    u0 = 0.02 * rng.standard_normal((3,) + solid.shape)
+    a = lbm.Solver(w, solid, rho, u0=u0)
+    b = lbm.Solver(w, solid, np.ones_like(rho))
+    b.step(7)
+    real = torch.float64 if storage == "F64" else torch.float32
+    b.reset(torch.tensor(rho.reshape(1, -1), dtype=real, device="cuda"),
+            torch.tensor(u0.reshape(3, -1), dtype=real, device="cuda"))
+    assert torch.equal(a.get_state(), b.get_state())
+    a.step(20)
+    b.step(20)
+    torch.cuda.synchronize()
+    assert torch.equal(a.get_state(), b.get_state())
+    assert a.stats()["mass"] == b.stats()["mass"]
 
 
 def test_mass_conservation_f32_and_stats():

@@ -207,7 +207,8 @@ def test_trained_network_gains_over_the_start_from_rest(T, ops):
     (the zero field, relative error 1); its permeability estimate is close to
     the solver's; and a warm start from it reaches the same permeability."""
     from paper_2506_17713_amd import inputs
-    from paper_2506_17713_amd.surrogate import Surrogate, make_dataset, solve_steady, targets_of, train, warm_fields
+    from paper_2506_17713_amd.surrogate import (Surrogate, calibrate_flow, make_dataset, solve_steady, targets_of,
+                                                train, warm_fields)
 
     D, radii, a = 32, (3.0, 7.0), 1e-5
     xs, ys, _ = make_dataset(32, D, radii=radii, log=lambda m: None)
@@ -216,16 +217,46 @@ def test_trained_network_gains_over_the_start_from_rest(T, ops):
     solid = inputs.sphere_pack((D,) * 3, radii, 0.4, 1000)
     cold = solve_steady(solid, accel=a)
     tgt = targets_of(cold, solid, a).astype(np.float64)
-    pred = model.predict(T.tensor((solid == 0).astype(np.float32)[None], device="cuda"))
+    mask = T.tensor((solid == 0).astype(np.float32)[None], device="cuda")
+    k_raw = float(model.predict(mask)[0].mean())
+    gain = calibrate_flow(model, xs, ys)
+    # the gain solves the least-squares normal equation over the training packs
+    kp = np.array([model.predict(x)[0].mean() for x in xs])
+    kt = np.array([float(y[0].astype(np.float64).mean()) for y in ys])
+    assert abs(float(((kp - kt) * kp).sum())) < 1e-6 * float((kp * kp).sum())
+    pred = model.predict(mask)
     err_u = float(np.linalg.norm(pred[:3] - tgt[:3]) / np.linalg.norm(tgt[:3]))
     err_k = abs(float(pred[0].mean()) - cold["k"]) / cold["k"]
     rho0, u0 = warm_fields(pred, solid, a)
     warm = solve_steady(solid, accel=a, u0=u0, rho0=rho0)
-    print(f"velocity error {err_u:.3f}, k error {err_k:.3f}, steps cold {cold['steps']} / {cold['k_steps']} "
+    print(f"velocity error {err_u:.3f}, k error {err_k:.3f} (gain {gain:.3f}; uncalibrated "
+          f"{abs(k_raw - cold['k']) / cold['k']:.3f}), steps cold {cold['steps']} / {cold['k_steps']} "
           f"warm {warm['steps']} / {warm['k_steps']} (residual rule / k rule)")
     assert err_u < 0.6
     assert err_k < 0.3
     assert abs(warm["k"] - cold["k"]) < 1e-3 * cold["k"]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_warm_start_on_device_matches_host_fields(T, ops, dtype):
+    """warm_start_device (lbm_nn_warm_fields on the raw network output) forms
+    the start that warm_fields forms on the host from predict()."""
+    from paper_2506_17713_amd import inputs
+    from paper_2506_17713_amd.surrogate import Surrogate, warm_fields, warm_start_device
+
+    solid = inputs.sphere_pack((16, 24, 32), (3.0, 5.0), 0.4, seed=4)
+    mask = T.tensor((solid == 0).astype(np.float32)[None], device="cuda")
+    model = Surrogate(prec=ops.FP32, seed=2)
+    model.scale = np.array([0.7, 0.2, 0.3, 5.0])
+    model.flow_gain = 0.9
+    a = 1e-5
+    rho_h, u_h = warm_fields(model.predict(mask), solid, a)
+    rho_d, u_d = warm_start_device(model, mask, a, dtype=getattr(T, dtype))
+    tol = 1e-13 if dtype == "float64" else 1e-6
+    assert rho_d.dtype == getattr(T, dtype)
+    assert np.abs(rho_d.cpu().numpy().astype(np.float64) - rho_h).max() < tol * 1.0
+    assert np.abs(u_d.cpu().numpy().astype(np.float64) - u_h).max() < tol * np.abs(u_h).max() + 1e-30
+    assert np.all(rho_d.cpu().numpy()[0][solid.reshape(-1) != 0] == 1.0)
 
 
 @pytest.mark.parametrize("shift,flip,swap", [((1, 2, 3), (0, 0, 0), False), ((0, 5, 7), (1, 0, 1), True),
