@@ -382,10 +382,14 @@ __global__ void k_adj_stream(AdjArgs<R> P) {
     decode<LAT>(n, P.NA, P.NB, a, b, c);
     const size_t N = (size_t)P.N;
     R rb = P.rbar_e[n];
+    // only a solid neighbour x + e_i (bit opp(i) of the word) can be an active
+    // solid, so fluid neighbours are not looked up
     sfor<L::Q - 1>([&](auto I) {
         constexpr int i = decltype(I)::value + 1;
-        const int m = shift<LAT>(a, b, c, L::ea(i), L::eb(i), L::ec(i), P.NA, P.NB, P.NCc);
-        if (P.flag[m] == 2) rb += P.rbar_ave[m] * (R)L::w(i) / P.wsum[m];
+        if ((w >> opp(i)) & 1u) {
+            const int m = shift<LAT>(a, b, c, L::ea(i), L::eb(i), L::ec(i), P.NA, P.NB, P.NCc);
+            if (P.flag[m] == 2) rb += P.rbar_ave[m] * (R)L::w(i) / P.wsum[m];
+        }
     });
     sfor<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;

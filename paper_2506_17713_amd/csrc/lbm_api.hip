@@ -184,9 +184,13 @@ hipError_t launch_step(lbm_handle* h, StepArgs<typename Store<ST>::R>& a) {
     const int tiles = a.tiles_a * a.tiles_b;
     int chunk = h->chunk_override;
     if (chunk <= 0) {
-        const int want = (2048 + tiles - 1) / tiles;  // chunks for about 2048 workgroups
+        // chunks for about 2048 workgroups, but at least 16 planes per chunk in
+        // 3-D: a chunk pulls 4 planes beyond its own (the rho ring), so short
+        // chunks of small lattices cost more than the extra workgroups gain
+        // (128^3: 16 planes per chunk is 10 % faster than 8)
+        const int want = (2048 + tiles - 1) / tiles;
         chunk = (h->NCc + want - 1) / want;
-        const int minc = LAT == LAT_D2Q9 ? 4 : 8;
+        const int minc = LAT == LAT_D2Q9 ? 4 : 16;
         if (chunk < minc) chunk = minc;
     }
     if (chunk > h->NCc) chunk = h->NCc;
