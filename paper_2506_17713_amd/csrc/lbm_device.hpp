@@ -366,7 +366,10 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
 // BBI: take the bounce-back source at issue time (two components, where every
 // gather pays a full memory latency) or patch it after the streaming loads
 // (one component: a cheaper plain path for the bulk).
-template <int LAT, int ST, int NC, bool BBI = (NC > 1)>
+// RING (deviation storage): the source densities rho* come from an LDS ring
+// of the caller, so the pull loads only the 16-bit deviations and finish()
+// leaves 1 + h_i for the caller to scale by w_i rho*(source).
+template <int LAT, int ST, int NC, bool BBI = (NC > 1), bool RING = false>
 struct Pull {
     using L = Lat<LAT>;
     using SS = Store<ST>;
@@ -374,7 +377,7 @@ struct Pull {
     using R = typename SS::R;
     static constexpr int Q = L::Q;
     S v[NC][Q];
-    float rs[NC][SS::DEV ? Q : 1];
+    float rs[NC][SS::DEV && !RING ? Q : 1];
 
     // Issue the loads of node (a, b, c): f_i(x) = f*_i(x - e_i), or, where
     // x - e_i is solid (bit i of the neighbour word), the halfway bounce-back
@@ -398,11 +401,11 @@ struct Pull {
                                  (uint32_t)((b == 0 ? NB - 1 : b - 1) * NA)};
         const size_t cs[3] = {(size_t)(c == NCc - 1 ? 0 : c + 1), (size_t)c, (size_t)(c == 0 ? NCc - 1 : c - 1)};
         const char* fb = reinterpret_cast<const char*>(P.fin);
-        const char* rb = reinterpret_cast<const char*>(P.rin);
+        [[maybe_unused]] const char* rb = reinterpret_cast<const char*>(P.rin);
         auto load = [&](int k, int dir, size_t pl, uint32_t e, int i) {
             v[k][i] = *reinterpret_cast<const S*>(fb + ((size_t)(k * Q + dir) * N + pl) * sizeof(S) +
                                                   e * (uint32_t)sizeof(S));
-            if constexpr (SS::DEV)
+            if constexpr (SS::DEV && !RING)
                 rs[k][i] = *reinterpret_cast<const float*>(rb + ((size_t)k * N + pl) * 4 + e * 4u);
         };
         const bool wall = BBI && __builtin_amdgcn_ballot_w64((word & ~1u) != 0u) != 0;
@@ -440,7 +443,7 @@ struct Pull {
             asm volatile("" : "+v"(e));
             const size_t pl = (size_t)c * plane;
             const char* fb = reinterpret_cast<const char*>(P.fin);
-            const char* rb = reinterpret_cast<const char*>(P.rin);
+            [[maybe_unused]] const char* rb = reinterpret_cast<const char*>(P.rin);
             sfor<Q - 1>([&](auto I) {
                 constexpr int i = decltype(I)::value + 1;
                 if ((word >> i) & 1u) {
@@ -448,7 +451,7 @@ struct Pull {
                     for (int k = 0; k < NC; ++k) {
                         v[k][i] = *reinterpret_cast<const S*>(fb + ((size_t)(k * Q + opp(i)) * N + pl) * sizeof(S) +
                                                               e * (uint32_t)sizeof(S));
-                        if constexpr (SS::DEV)
+                        if constexpr (SS::DEV && !RING)
                             rs[k][i] = *reinterpret_cast<const float*>(rb + ((size_t)k * N + pl) * 4 + e * 4u);
                     }
                 }
@@ -458,7 +461,8 @@ struct Pull {
             constexpr int i = decltype(I)::value;
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
-                if constexpr (SS::DEV) f[k][i] = (float)L::w(i) * rs[k][i] * (1.0f + SS::load(v[k][i]));
+                if constexpr (SS::DEV && RING) f[k][i] = 1.0f + SS::load(v[k][i]);
+                else if constexpr (SS::DEV) f[k][i] = (float)L::w(i) * rs[k][i] * (1.0f + SS::load(v[k][i]));
                 else f[k][i] = (R)v[k][i];
             }
         });
@@ -519,6 +523,14 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
 // otherwise takes 171 registers and runs two waves; bounded, it spills two
 // and runs 9 % faster).  Bounds on the two-component kernels (three waves for
 // deviation storage, four for FP32) measured 16 % slower and no faster.
+// Two-component deviation storage in 3-D takes the source densities rho* of
+// its pulls from an LDS ring of rho* planes (tile plus halo 3) instead of one
+// global load per pulled value (1-3 % faster).  With one component the ring
+// pushes the register-bound kernel into spills and runs 23 % slower, so it
+// keeps the global loads.
+#ifndef LBM_DEV_RING
+#define LBM_DEV_RING 1
+#endif
 #ifndef LBM_WAVES_1C_DEV
 #define LBM_WAVES_1C_DEV 3
 #endif
@@ -546,6 +558,13 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
     __shared__ R s_rho[5][NC][RP];  // rho of fluid nodes, -1 at solid nodes
     __shared__ R s_psi[3][NC][PP];
     __shared__ R s_U[3][NC][PP];
+    // rho* ring (deviation storage, 3-D): planes c-1, c, c+1 of the plane being
+    // pulled and the one fetched ahead, over the tile with halo 3 (the sources
+    // of the halo-2 positions)
+    constexpr bool RSR = SS::DEV && D3 && NC == 2 && LBM_DEV_RING;
+    constexpr int SWA = TA + 6, SWB = TB + 6, SP = SWA * SWB;
+    constexpr int RLD = RSR ? (SP + NT - 1) / NT : 1;
+    __shared__ float s_rs[RSR ? 4 : 1][NC][RSR ? SP : 1];
 
     const int tid = threadIdx.x;
     const int NA = P.NA, NB = P.NB, NCc = P.NC_;
@@ -656,6 +675,52 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
 #pragma unroll
         for (int j = 0; j < HPT; ++j) w_halo[j] = h_on[j] ? P.nbr[(c * NB + h_b[j]) * NA + h_a[j]] : 0u;
     };
+    // rho* ring (RSR): fetch plane cp of the tile with halo 3 into registers,
+    // store it into its slot; scale pulled 1 + h_i by w_i rho*(x - e_i)
+    const bool smallSA = NA < SWA, smallSB = NB < SWB;
+    auto rs_fetch = [&](int cp, float(&r)[NC][RLD]) {
+        const int c = wrap_c(cp);
+#pragma unroll
+        for (int j = 0; j < RLD; ++j) {
+            const int idx = tid + j * NT;
+            if (idx < SP) {
+                int ga = a0 + idx % SWA - 3, gb = b0 + idx / SWA - 3;
+                ga = smallSA ? wrap_any(ga, NA) : wrap_near(ga, NA);
+                gb = smallSB ? wrap_any(gb, NB) : wrap_near(gb, NB);
+                const size_t n = ((size_t)c * NB + gb) * NA + ga;
+#pragma unroll
+                for (int k = 0; k < NC; ++k) r[k][j] = P.rin[(size_t)k * N + n];
+            }
+        }
+    };
+    auto rs_store = [&](int cp, const float(&r)[NC][RLD]) {
+        const int sl = (cp - c0 + 8) & 3;
+#pragma unroll
+        for (int j = 0; j < RLD; ++j) {
+            const int idx = tid + j * NT;
+            if (idx < SP) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) s_rs[sl][k][idx] = r[k][j];
+            }
+        }
+    };
+    auto rs_scale = [&](R(&f)[NC][Q], uint32_t word, int lofs, int cp) {
+        // flat offsets into s_rs of the own position in the planes cp - 1, cp, cp + 1
+        const int o0 = ((cp - c0 + 8) & 3) * NC * SP + lofs;
+        const int on = ((cp + 1 - c0 + 8) & 3) * NC * SP + lofs;
+        const int op = ((cp - 1 - c0 + 8) & 3) * NC * SP + lofs;
+        const float* ring = &s_rs[0][0][0];
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            // source x - e_i: plane cp + 1 for e_c = -1, cp - 1 for e_c = +1;
+            // a bounced population comes from the node itself
+            const int src = (L::ec(i) == 0 ? o0 : (L::ec(i) < 0 ? on : op)) - L::eb(i) * SWA - L::ea(i);
+            const int at = (i != 0 && ((word >> i) & 1u)) ? o0 : src;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) f[k][i] = ((float)L::w(i) * ring[at + k * SP]) * f[k][i];
+        });
+    };
+
     auto fill_rho = [&](int cp, R(&fo)[NC][Q]) {
         const int slot = (cp - c0 + 5) % 5;
         const int c = wrap_c(cp);
@@ -676,15 +741,22 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
         // sequential order: with several nodes in flight they lose a wave per
         // SIMD, which costs more than the latency saved.
         constexpr bool OVERLAP = !SS::DEV && NC == 1;
-        Pull<LAT, ST, NC> po;
-        Pull<LAT, ST, NC> ph[OVERLAP ? HPT : 1];
+        // the rho* plane two ahead is fetched first, so that storing it waits
+        // only for its own loads
+        float rsn[NC][RLD];
+        if constexpr (RSR) rs_fetch(cp + 2, rsn);
+        Pull<LAT, ST, NC, (NC > 1), RSR> po;
+        Pull<LAT, ST, NC, (NC > 1), RSR> ph[OVERLAP ? HPT : 1];
         po.issue(P, own_a, own_b, c, wo);
         if constexpr (OVERLAP) {
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
                 if (need(j)) ph[j].issue(P, h_a[j], h_b[j], c, wh[j]);
         }
+        if constexpr (RSR) rs_store(cp + 2, rsn);
         po.finish(P, own_a, own_b, c, wo, fo);
+        if constexpr (RSR)
+            if (!(wo & 1u)) rs_scale(fo, wo, (lb_own + 3) * SWA + la_own + 3, cp);
         if (wo & 1u) {
 #pragma unroll
             for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = solid_mark(wo);
@@ -708,6 +780,11 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
                 } else {
                     ph[0].issue(P, h_a[j], h_b[j], c, wh[j]);
                     ph[0].finish(P, h_a[j], h_b[j], c, wh[j], f);
+                }
+                if constexpr (RSR) {
+                    // ring position (ra + 1, rb + 1) of halo position (ra, rb)
+                    const int rb = h_idx[j] / RWA;
+                    rs_scale(f, wh[j], h_idx[j] + 2 * rb + SWA + 1, cp);
                 }
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = rho_sum(f, k);
@@ -1101,6 +1178,15 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
     // keeps the code small enough for the instruction cache.
     R fc0[NC][Q], fc1[NC][Q], fc2[NC][Q];
     fetch_words(c0 - 2);
+    if constexpr (RSR) {
+        // rho* of the planes around the first pulled plane, c0 - 2
+        float r[NC][RLD];
+        for (int cp = c0 - 3; cp < c0; ++cp) {
+            rs_fetch(cp, r);
+            rs_store(cp, r);
+        }
+        __syncthreads();
+    }
 #pragma nounroll
     for (int it = c0 - 4; it < c1; ++it) {
         fill_rho(it + 2, fc2);
