@@ -177,7 +177,7 @@ def main():
     if args.steps is None:
         args.steps = 1000 if args.workload == "adjoint" else 500
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU x-slab sharding is "
+        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU x-slab sharding is "
                                    "described in DESIGN.md and not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np

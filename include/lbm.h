@@ -39,7 +39,7 @@ extern "C" {
 typedef enum lbm_error {
     LBM_OK = 0,
     LBM_ERR_ARG = -1,         /* invalid argument or parameter combination   */
-    LBM_ERR_UNSUPPORTED = -2, /* valid but not provided by this build         */
+    LBM_ERR_UNSUPPORTED = -2, /* valid but not provided by this library       */
     LBM_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed   */
     LBM_ERR_NONFINITE = -4,   /* a check found a non-finite or negative rho   */
     LBM_ERR_SPACE = -5        /* workspace smaller than lbm_workspace_size   */

@@ -8,7 +8,7 @@ Here the network maps the pore mask to the steady fields in units that do not
 depend on the forcing: u nu / a (three channels) and the pressure deviation
 (rho - 1) c_s^2 / a (one channel, a length).  The solver then starts from
 f = f^eq(rho_pred, u_pred - a/2) and runs to the same stopping rule, so the
-plain solver remains the judge of the permeability.  The pressure channel
+plain solver remains the arbiter of the permeability.  The pressure channel
 matters: the steady density is not uniform (about +-0.2 % in these packs),
 and a start from the exact velocity with rho = 1 converges no faster than a
 start from rest because the pressure has to build up first.

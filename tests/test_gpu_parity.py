@@ -8,6 +8,7 @@ checked on sampled nodes, each recomputed by the oracle on a periodic crop
 wider than the dependency cone of the steps taken."""
 import json
 import os
+import tempfile
 
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ from paper_2506_17713_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-OUT = os.environ.get("LBM_TEST_REPORT", "gpurun_out/parity_report.jsonl")
+OUT = os.environ.get("LBM_TEST_REPORT", os.path.join(tempfile.gettempdir(), "lbm_parity_report.jsonl"))
 
 
 def _report(rec):
