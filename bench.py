@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=None, help="lattice size (default: 256, 128 for droplet2d, "
                                                          "400 for pack2)")
-    ap.add_argument("--workload", default="sessile", choices=["sessile", "droplet2d", "pack2", "adjoint"],
+    ap.add_argument("--workload", default="sessile", choices=["sessile", "droplet2d", "pack2", "adjoint", "surrogate"],
                     help="sessile: D3Q19 MRT sessile droplet (the headline line); droplet2d: D2Q9 BGK FP64 "
                          "droplet; pack2: D3Q19 two-component sphere pack; adjoint: gradient of the "
                          "saturation over 1000 steps of the 128^3 pack (checkpoint every 100)")
@@ -172,10 +172,86 @@ def run_adjoint(args) -> dict:
     }
 
 
+def conv_flops(arch, size: int) -> dict:
+    """Multiply-add FLOPs (2 per MAC) of the surrogate's 3x3x3 convolutions on
+    a size^3 input: forward, and a training step's backward (data gradient of
+    every layer but the first, weight gradient of every layer)."""
+    level = {"enc0": 0, "dec0": 0, "head": 0, "enc1": 1, "dec1": 1, "enc2": 2, "dec2": 2, "bot": 3}
+    fwd = bwd = 0.0
+    for name, ci, co in arch:
+        lv = next(v for k, v in level.items() if name.startswith(k))
+        f = 2.0 * ci * co * 27 * (size >> lv) ** 3
+        fwd += f
+        bwd += f + (f if name != "enc0a" else 0.0)
+    return {"forward": fwd, "backward": bwd}
+
+
+def run_surrogate(args) -> dict:
+    """Surrogate throughput: inference on a 256^3 pack and training steps
+    (forward, masked MSE, backward, Adam) on 128^3 packs, BF16 MFMA.  The
+    timed regions hold every kernel of the pass (pooling, upsampling, ReLU and
+    skip additions besides the convolutions); the FLOPs counted are the
+    convolutions'."""
+    import numpy as np
+    import torch
+
+    from paper_2506_17713_amd import inputs, nn
+    from paper_2506_17713_amd.surrogate import ARCH, Surrogate
+
+    model = Surrogate(prec=nn.BF16, seed=0)
+    st = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    big = torch.tensor((inputs.sphere_pack((256,) * 3, (6.0, 14.0), 0.4, 1000) == 0).astype(np.float32)[None],
+                       device="cuda")
+    t_inf = timed(lambda: model.forward(big), args.steps)
+    small = torch.tensor((inputs.sphere_pack((128,) * 3, (6.0, 14.0), 0.4, 7) == 0).astype(np.float32)[None],
+                         device="cuda")
+    target = torch.zeros((4, 128, 128, 128), dtype=torch.float32, device="cuda")
+
+    def train_step():
+        tape = []
+        out = model.forward(small, tape)
+        _, dout = nn.mse(out, target, small[0])
+        model.adam_step(model.backward(tape, dout), 1e-4)
+
+    t_train = timed(train_step, args.steps)
+    f256, f128 = conv_flops(ARCH, 256), conv_flops(ARCH, 128)
+    inf_tf = f256["forward"] / t_inf / 1e12
+    train_tf = (f128["forward"] + f128["backward"]) / t_train / 1e12
+    return {
+        "metric": "TFLOP/s of the surrogate's 3x3x3 convolutions (BF16 MFMA, FP32 accumulation), inference",
+        "value": round(inf_tf, 2), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_inf * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "surrogate U-Net (15 periodic 3x3x3 convolutions, 1.32 M parameters), inference "
+                               "on a 256^3 pack; training steps on 128^3",
+                   "inference_ms": round(t_inf * 1e3, 3), "inference_conv_TFLOP": round(f256["forward"] / 1e12, 4),
+                   "train_step_ms": round(t_train * 1e3, 3),
+                   "train_step_conv_TFLOP": round((f128["forward"] + f128["backward"]) / 1e12, 4),
+                   "train_TFLOP_s": round(train_tf, 2)},
+        "roofline": {"bound": "mfma", "achieved": round(inf_tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(inf_tf / 2500.0, 4), "traffic": None,
+                     "kernel": "whole inference pass (convolutions' FLOPs over all kernels' time)"},
+        "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.steps is None:
-        args.steps = 1000 if args.workload == "adjoint" else 500
+        args.steps = {"adjoint": 1000, "surrogate": 20}.get(args.workload, 500)
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU only; multi-GPU x-slab sharding is "
                                    "described in DESIGN.md and not implemented", "n_gpus": args.gpus}))
@@ -187,6 +263,9 @@ def main():
 
     if args.workload == "adjoint":
         print(json.dumps(run_adjoint(args)), flush=True)
+        return
+    if args.workload == "surrogate":
+        print(json.dumps(run_surrogate(args)), flush=True)
         return
     n = args.n or {"sessile": 256, "droplet2d": 128, "pack2": 400}[args.workload]
     storage = args.storage if args.workload != "droplet2d" or args.storage != "F32" else "F64"

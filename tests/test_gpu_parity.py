@@ -177,6 +177,13 @@ def test_deviation_storage_error_is_reported(oracle_mod, storage):
     out1, _, _ = run_pair(oracle_mod, w1, solid1, rho1, 300)
     for c, (er, eu) in out1.items():
         assert er < band, (c, er)
+    # ragged planes (37 x 45): the last tile row and the tile column wrap, and
+    # the rho* ring of the two-component kernel covers wrapped halos
+    w2, solid2, rho2 = inputs.two_component_pack(shape=(34, 37, 45), storage=storage, radii=(4.0, 7.0), seed=3)
+    out2, _, rec2 = run_pair(oracle_mod, w2, solid2, rho2, 100)
+    for c, (er, eu) in out2.items():
+        assert er < band, (c, er)
+    assert max(rec2["mass_rel_err"]) < 1e-3
 
 
 # --------------------------------------------------- full-size sampled parity
