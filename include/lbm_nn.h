@@ -51,8 +51,10 @@ size_t lbm_nn_wgrad_partial_words(int c_out, int c_in, int D, int H, int W);
 int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, int H, int W, float* dW,
                  float* partial, int prec, void* stream);
 
-/* db[c] = sum_p dY[c][p] (overwrites). */
-int lbm_nn_bias_grad(const float* dY, int c, int64_t P, float* db, void* stream);
+/* db[c] = sum_p dY[c][p] (overwrites), summed in double in a fixed order
+ * (64 chunks per channel, then the chunk sums in order).  scratch: device
+ * double[64 c].  Errors: LBM_ERR_ARG (c < 1, c > 65535, P < 1, NULL), LBM_ERR_HIP. */
+int lbm_nn_bias_grad(const float* dY, int c, int64_t P, float* db, double* scratch, void* stream);
 /* dY[i] *= (Y[i] > 0) */
 int lbm_nn_relu_bwd(const float* Y, float* dY, int64_t n, void* stream);
 /* y[i] += x[i] */

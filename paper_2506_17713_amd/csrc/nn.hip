@@ -177,16 +177,30 @@ __global__ void k_chunk_sum(const float* __restrict__ partial, int nchunk, int64
     out[i] = s;
 }
 
-__global__ void __launch_bounds__(256) k_bias_grad(const float* __restrict__ dY, int64_t P, float* __restrict__ db) {
-    const int c = blockIdx.x;
+// Bias gradient in two fixed-order passes: block (j, c) sums chunk j of
+// channel c in double, then one thread per channel adds the chunk sums.
+constexpr int kBiasChunks = 64;
+__global__ void __launch_bounds__(256) k_bias_partial(const float* __restrict__ dY, int64_t P,
+                                                      double* __restrict__ part) {
+    const int j = blockIdx.x, c = blockIdx.y;
+    const int64_t per = (P + kBiasChunks - 1) / kBiasChunks;
+    const int64_t p0 = j * per, p1 = p0 + per < P ? p0 + per : P;
     double s = 0.0;
-    for (int64_t p = threadIdx.x; p < P; p += 256) s += dY[(size_t)c * P + p];
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) s += dY[(size_t)c * P + p];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     __shared__ double sh[4];
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) db[c] = (float)(sh[0] + sh[1] + sh[2] + sh[3]);
+    if (threadIdx.x == 0) part[(size_t)c * kBiasChunks + j] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void k_bias_final(const double* __restrict__ part, int C, float* __restrict__ db) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < kBiasChunks; ++j) s += part[(size_t)c * kBiasChunks + j];
+        db[c] = (float)s;
+    }
 }
 
 __global__ void k_relu_bwd(const float* __restrict__ Y, float* __restrict__ dY, int64_t n) {
@@ -472,9 +486,11 @@ int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, in
     return ok(hipGetLastError());
 }
 
-int lbm_nn_bias_grad(const float* dY, int c, int64_t P, float* db, void* stream) {
-    if (!dY || !db || c < 1) return LBM_ERR_ARG;
-    hipLaunchKernelGGL(k_bias_grad, dim3(c), dim3(256), 0, (hipStream_t)stream, dY, P, db);
+int lbm_nn_bias_grad(const float* dY, int c, int64_t P, float* db, double* scratch, void* stream) {
+    if (!dY || !db || !scratch || c < 1 || c > 65535 || P < 1) return LBM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_bias_partial, dim3(kBiasChunks, c), dim3(256), 0, st, dY, P, scratch);
+    hipLaunchKernelGGL(k_bias_final, dim3((c + 127) / 128), dim3(128), 0, st, scratch, c, db);
     return ok(hipGetLastError());
 }
 

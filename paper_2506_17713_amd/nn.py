@@ -31,7 +31,7 @@ def load():
         lib.lbm_nn_wgrad_partial_words.argtypes = [i, i, i, i, i]
         lib.lbm_nn_wgrad_partial_words.restype = C.c_size_t
         lib.lbm_nn_wgrad.argtypes = [vp, i, vp, i, i, i, i, vp, vp, i, vp]
-        lib.lbm_nn_bias_grad.argtypes = [vp, i, i64, vp, vp]
+        lib.lbm_nn_bias_grad.argtypes = [vp, i, i64, vp, vp, vp]
         lib.lbm_nn_relu_bwd.argtypes = [vp, vp, i64, vp]
         lib.lbm_nn_add.argtypes = [vp, vp, i64, vp]
         lib.lbm_nn_pool.argtypes = [vp, i, i, i, i, vp, vp]
@@ -95,7 +95,8 @@ def wgrad(X: torch.Tensor, dY: torch.Tensor, prec=BF16) -> torch.Tensor:
 def bias_grad(dY: torch.Tensor) -> torch.Tensor:
     c = dY.shape[0]
     db = torch.empty(c, dtype=torch.float32, device=dY.device)
-    _chk("lbm_nn_bias_grad", load().lbm_nn_bias_grad(_p(dY), c, dY[0].numel(), _p(db), _s()))
+    scratch = torch.empty(64 * c, dtype=torch.float64, device=dY.device)
+    _chk("lbm_nn_bias_grad", load().lbm_nn_bias_grad(_p(dY), c, dY[0].numel(), _p(db), _p(scratch), _s()))
     return db
 
 
