@@ -41,9 +41,13 @@ size_t lbm_nn_packed_words(int c_out, int c_in);
 int lbm_nn_pack(const float* W, int c_out, int c_in, int transpose, int prec, uint32_t* packed, void* stream);
 
 /* Y[co] = act(bias[co] + sum_ci sum_t W[co][ci][t] X[ci][p + off(t)]) + skip[co]
- * act = max(0, .) when relu != 0; bias and skip may be NULL. */
+ * act = max(0, .) when relu != 0; bias and skip may be NULL.  work: device
+ * buffer of lbm_nn_conv_work_bytes() bytes, which receives X converted to
+ * BF16 with channels innermost (BF16 only; FP32 takes NULL).
+ * Errors: LBM_ERR_ARG (bad sizes, P max(c_in, c_out) >= 2^31, no work for BF16), LBM_ERR_HIP. */
+size_t lbm_nn_conv_work_bytes(int c_in, int D, int H, int W, int prec);
 int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* bias, const float* skip,
-                float* Y, int c_out, int D, int H, int W, int relu, int prec, void* stream);
+                float* Y, int c_out, int D, int H, int W, int relu, int prec, void* work, void* stream);
 
 /* dW[co][ci][t] = sum_p dY[co][p] X[ci][p + off(t)] (overwrites dW).
  * partial: device scratch of lbm_nn_wgrad_partial_words(c_out, c_in, D, H, W) floats. */

@@ -60,10 +60,31 @@ __global__ void k_pack(const float* __restrict__ W, int cout, int cin, int trans
     }
 }
 
+// Input of a BF16 convolution converted once: Xb[p][cin_pad] (BF16, channels
+// innermost, zero beyond cin), so that a lane's B operand (4 channels at one
+// position) is one 8-byte load.  Thread i converts channel group g = i % G of
+// position p = i / G: consecutive lanes write consecutive 8-byte words, and
+// the lanes of one group read consecutive positions of a channel plane.
+__global__ void k_act_pack(const float* __restrict__ X, int cin, int cip, int64_t P, bf16x4* __restrict__ Xb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int G = cip / 4;
+    if (i >= (int64_t)G * P) return;
+    const int64_t p = i / G;
+    const int g = (int)(i - p * G);
+    bf16x4 v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int ci = 4 * g + j;
+        v[j] = ci < cin ? f2bf(X[(size_t)ci * P + p]) : (short)0;
+    }
+    Xb[i] = v;
+}
+
 template <int PREC>
 __global__ void __launch_bounds__(256)
-    k_conv(const float* __restrict__ X, int cin, const uint32_t* __restrict__ packed, const float* __restrict__ bias,
-           const float* __restrict__ skip, float* __restrict__ Y, int cout, int D, int H, int W, int relu) {
+    k_conv(const float* __restrict__ X, const bf16x4* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
+           const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout, int D,
+           int H, int W, int relu) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int P = D * H * W;
     const int p = (blockIdx.x * 4 + wave) * 32 + (lane & 31);
@@ -81,14 +102,10 @@ __global__ void __launch_bounds__(256)
         const int q = (wrapc(z + dz, D) * H + wrapc(y + dy, H)) * W + wrapc(x + dx, W);
         if constexpr (PREC == LBM_NN_BF16) {
             const bf16x4* wp = reinterpret_cast<const bf16x4*>(packed);
+            const bf16x4 zero = {0, 0, 0, 0};
             for (int c8 = 0; c8 < cip; c8 += 8) {
                 const bf16x4 a = wp[((size_t)tap * (cip / 4) + c8 / 4 + kq) * cop + co0 + (lane & 31)];
-                bf16x4 b;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int ci = c8 + 4 * kq + j;
-                    b[j] = (pok && ci < cin) ? f2bf(X[(size_t)ci * P + q]) : (short)0;
-                }
+                const bf16x4 b = pok ? Xb[(size_t)q * (cip / 4) + c8 / 4 + kq] : zero;
                 acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
             }
         } else {
@@ -443,20 +460,31 @@ int lbm_nn_pack(const float* W, int c_out, int c_in, int transpose, int prec, ui
     return ok(hipGetLastError());
 }
 
+size_t lbm_nn_conv_work_bytes(int c_in, int D, int H, int W, int prec) {
+    if (prec != LBM_NN_BF16 || c_in < 1 || D < 1 || H < 1 || W < 1) return 0;
+    return (size_t)D * H * W * cin_pad_of(c_in, prec) * 2;
+}
+
 int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* bias, const float* skip, float* Y,
-                int c_out, int D, int H, int W, int relu, int prec, void* stream) {
+                int c_out, int D, int H, int W, int relu, int prec, void* work, void* stream) {
     if (!X || !packed || !Y || c_in < 1 || c_out < 1 || D < 1 || H < 1 || W < 1) return LBM_ERR_ARG;
     const int64_t P = (int64_t)D * H * W;
     if (P * (c_in > c_out ? c_in : c_out) >= (1LL << 31)) return LBM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
     dim3 grid((unsigned)((P + 127) / 128), (unsigned)((c_out + 31) / 32));
-    if (prec == LBM_NN_BF16)
-        hipLaunchKernelGGL(k_conv<LBM_NN_BF16>, grid, dim3(256), 0, (hipStream_t)stream, X, c_in, packed, bias,
-                           skip, Y, c_out, D, H, W, relu);
-    else if (prec == LBM_NN_FP32)
-        hipLaunchKernelGGL(k_conv<LBM_NN_FP32>, grid, dim3(256), 0, (hipStream_t)stream, X, c_in, packed, bias,
-                           skip, Y, c_out, D, H, W, relu);
-    else
+    if (prec == LBM_NN_BF16) {
+        if (!work) return LBM_ERR_ARG;
+        const int cip = cin_pad_of(c_in, prec);
+        bf16x4* Xb = reinterpret_cast<bf16x4*>(work);
+        hipLaunchKernelGGL(k_act_pack, dim3(grid1((int64_t)(cip / 4) * P)), dim3(256), 0, st, X, c_in, cip, P, Xb);
+        hipLaunchKernelGGL(k_conv<LBM_NN_BF16>, grid, dim3(256), 0, st, X, Xb, c_in, packed, bias, skip, Y, c_out,
+                           D, H, W, relu);
+    } else if (prec == LBM_NN_FP32) {
+        hipLaunchKernelGGL(k_conv<LBM_NN_FP32>, grid, dim3(256), 0, st, X, (const bf16x4*)nullptr, c_in, packed,
+                           bias, skip, Y, c_out, D, H, W, relu);
+    } else {
         return LBM_ERR_ARG;
+    }
     return ok(hipGetLastError());
 }
 

@@ -12,7 +12,7 @@ import torch
 from . import lbm
 
 BF16, FP32 = 0, 1
-EXPORTS = ["lbm_nn_packed_words", "lbm_nn_pack", "lbm_nn_conv", "lbm_nn_wgrad_partial_words", "lbm_nn_wgrad",
+EXPORTS = ["lbm_nn_packed_words", "lbm_nn_pack", "lbm_nn_conv_work_bytes", "lbm_nn_conv", "lbm_nn_wgrad_partial_words", "lbm_nn_wgrad",
            "lbm_nn_bias_grad", "lbm_nn_relu_bwd", "lbm_nn_add", "lbm_nn_pool", "lbm_nn_pool_bwd", "lbm_nn_up",
            "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam", "lbm_nn_augment", "lbm_nn_warm_fields"]
 
@@ -27,7 +27,9 @@ def load():
         lib.lbm_nn_packed_words.argtypes = [i, i]
         lib.lbm_nn_packed_words.restype = C.c_size_t
         lib.lbm_nn_pack.argtypes = [vp, i, i, i, i, vp, vp]
-        lib.lbm_nn_conv.argtypes = [vp, i, vp, vp, vp, vp, i, i, i, i, i, i, vp]
+        lib.lbm_nn_conv_work_bytes.argtypes = [i, i, i, i, i]
+        lib.lbm_nn_conv_work_bytes.restype = C.c_size_t
+        lib.lbm_nn_conv.argtypes = [vp, i, vp, vp, vp, vp, i, i, i, i, i, i, vp, vp]
         lib.lbm_nn_wgrad_partial_words.argtypes = [i, i, i, i, i]
         lib.lbm_nn_wgrad_partial_words.restype = C.c_size_t
         lib.lbm_nn_wgrad.argtypes = [vp, i, vp, i, i, i, i, vp, vp, i, vp]
@@ -43,7 +45,7 @@ def load():
         lib.lbm_nn_augment.argtypes = [vp, vp, i, i, i, i, vp, vp, i, vp, vp, vp]
         lib.lbm_nn_warm_fields.argtypes = [vp, vp, i64, vp, C.c_double, i, vp, vp, vp, vp]
         for n in EXPORTS:
-            if n not in ("lbm_nn_packed_words", "lbm_nn_wgrad_partial_words"):
+            if n not in ("lbm_nn_packed_words", "lbm_nn_wgrad_partial_words", "lbm_nn_conv_work_bytes"):
                 getattr(lib, n).restype = C.c_int
         _lib = lib
     return _lib
@@ -76,9 +78,12 @@ def pack(W: torch.Tensor, transpose: bool, prec: int) -> torch.Tensor:
 def conv(X: torch.Tensor, packed: torch.Tensor, c_out: int, bias=None, skip=None, relu=False, prec=BF16,
          out=None) -> torch.Tensor:
     c_in, D, H, W = X.shape
+    lib = load()
     Y = torch.empty((c_out, D, H, W), dtype=torch.float32, device=X.device) if out is None else out
-    _chk("lbm_nn_conv", load().lbm_nn_conv(_p(X), c_in, _p(packed), _p(bias), _p(skip), _p(Y), c_out, D, H, W,
-                                           int(relu), prec, _s()))
+    wb = lib.lbm_nn_conv_work_bytes(c_in, D, H, W, prec)
+    work = torch.empty(wb, dtype=torch.uint8, device=X.device) if wb else None
+    _chk("lbm_nn_conv", lib.lbm_nn_conv(_p(X), c_in, _p(packed), _p(bias), _p(skip), _p(Y), c_out, D, H, W,
+                                        int(relu), prec, _p(work), _s()))
     return Y
 
 
