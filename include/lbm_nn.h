@@ -50,7 +50,8 @@ int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* b
                 float* Y, int c_out, int D, int H, int W, int relu, int prec, void* work, void* stream);
 
 /* dW[co][ci][t] = sum_p dY[co][p] X[ci][p + off(t)] (overwrites dW).
- * partial: device scratch of lbm_nn_wgrad_partial_words(c_out, c_in, D, H, W) floats. */
+ * partial: device scratch of lbm_nn_wgrad_partial_words(c_out, c_in, D, H, W) floats (tile partials, and
+ * for BF16 the operands converted once). */
 size_t lbm_nn_wgrad_partial_words(int c_out, int c_in, int D, int H, int W);
 int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, int H, int W, float* dW,
                  float* partial, int prec, void* stream);

@@ -133,10 +133,16 @@ __global__ void __launch_bounds__(256)
 
 // Weight gradient partial tiles: one wave per (co block, n block, position chunk),
 // n = ci * 27 + tap.
+// FP32 -> BF16 (round to nearest even), elementwise.
+__global__ void k_to_bf16(const float* __restrict__ x, short* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
 template <int PREC>
 __global__ void __launch_bounds__(64)
     k_wgrad(const float* __restrict__ X, int cin, const float* __restrict__ dY, int cout, int D, int H, int W,
-            int chunk, float* __restrict__ partial) {
+            int chunk, float* __restrict__ partial, const short* __restrict__ Xh, const short* __restrict__ dYh) {
     const int lane = threadIdx.x;
     const int P = D * H * W;
     const int co0 = blockIdx.x * 32, n0 = blockIdx.y * 32, ch = blockIdx.z;
@@ -155,24 +161,25 @@ __global__ void __launch_bounds__(64)
     constexpr int KS = 2 * KW;
     for (int pk = p0; pk < p1; pk += KS) {
         float av[KW], bv[KW];
+        [[maybe_unused]] bf16x4 ah, bh;
 #pragma unroll
         for (int j = 0; j < KW; ++j) {
             const int p = pk + kq * KW + j;
             const bool ok = p < p1;
             const int pp = ok ? p : p0;
-            av[j] = (ok && mok) ? dY[(size_t)m * P + pp] : 0.0f;
             const int x = pp % W, y = (pp / W) % H, z = pp / (W * H);
             const int q = (wrapc(z + dz, D) * H + wrapc(y + dy, H)) * W + wrapc(x + dx, W);
-            bv[j] = (ok && nok) ? X[(size_t)ci * P + q] : 0.0f;
+            if constexpr (PREC == LBM_NN_BF16) {
+                // operands converted once by the launcher (same rounding)
+                ah[j] = (ok && mok) ? dYh[(size_t)m * P + pp] : (short)0;
+                bh[j] = (ok && nok) ? Xh[(size_t)ci * P + q] : (short)0;
+            } else {
+                av[j] = (ok && mok) ? dY[(size_t)m * P + pp] : 0.0f;
+                bv[j] = (ok && nok) ? X[(size_t)ci * P + q] : 0.0f;
+            }
         }
         if constexpr (PREC == LBM_NN_BF16) {
-            bf16x4 a, b;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                a[j] = f2bf(av[j]);
-                b[j] = f2bf(bv[j]);
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc, 0, 0, 0);
         } else {
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bv[0], acc, 0, 0, 0);
         }
@@ -488,9 +495,14 @@ int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* b
     return ok(hipGetLastError());
 }
 
+// partial buffer: FP32 tile partials, then (aligned) the BF16 copies of X and dY
+static size_t wgrad_tiles_words(int c_out, int c_in, int64_t P) {
+    return ((size_t)wgrad_chunks(P) * c_out * c_in * 27 + 63) / 64 * 64;
+}
+
 size_t lbm_nn_wgrad_partial_words(int c_out, int c_in, int D, int H, int W) {
     const int64_t P = (int64_t)D * H * W;
-    return (size_t)wgrad_chunks(P) * c_out * c_in * 27;
+    return wgrad_tiles_words(c_out, c_in, P) + ((size_t)(c_in + c_out) * P + 1) / 2;
 }
 
 int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, int H, int W, float* dW,
@@ -503,12 +515,20 @@ int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, in
     chunk = (chunk + KS - 1) / KS * KS;
     dim3 grid((unsigned)((c_out + 31) / 32), (unsigned)((c_in * 27 + 31) / 32), (unsigned)nch);
     hipStream_t st = (hipStream_t)stream;
-    if (prec == LBM_NN_BF16)
-        hipLaunchKernelGGL(k_wgrad<LBM_NN_BF16>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk, partial);
-    else if (prec == LBM_NN_FP32)
-        hipLaunchKernelGGL(k_wgrad<LBM_NN_FP32>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk, partial);
-    else
+    if (prec == LBM_NN_BF16) {
+        short* Xh = reinterpret_cast<short*>(partial + wgrad_tiles_words(c_out, c_in, P));
+        short* dYh = Xh + (size_t)c_in * P;
+        hipLaunchKernelGGL(k_to_bf16, dim3(grid1((int64_t)c_in * P)), dim3(256), 0, st, X, Xh, (int64_t)c_in * P);
+        hipLaunchKernelGGL(k_to_bf16, dim3(grid1((int64_t)c_out * P)), dim3(256), 0, st, dY, dYh,
+                           (int64_t)c_out * P);
+        hipLaunchKernelGGL(k_wgrad<LBM_NN_BF16>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk, partial,
+                           (const short*)Xh, (const short*)dYh);
+    } else if (prec == LBM_NN_FP32) {
+        hipLaunchKernelGGL(k_wgrad<LBM_NN_FP32>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk, partial,
+                           (const short*)nullptr, (const short*)nullptr);
+    } else {
         return LBM_ERR_ARG;
+    }
     const int64_t n = (int64_t)c_out * c_in * 27;
     hipLaunchKernelGGL(k_chunk_sum, dim3(grid1(n)), dim3(256), 0, st, partial, nch, n, dW);
     return ok(hipGetLastError());
