@@ -135,3 +135,23 @@ def test_warm_start_driver_evaluates_a_loaded_model_without_training_it():
     assert warmstart.parse_args([]).train == 256
     assert warmstart.parse_args(["--load-model", "m.npz"]).train == 0
     assert warmstart.parse_args(["--load-model", "m.npz", "--train", "64"]).train == 64
+
+
+def test_surrogate_flop_count_matches_the_layer_shapes():
+    """bench.py's FLOP count of the surrogate: 2 per multiply-add of every
+    3x3x3 convolution at its level's size; a training step adds the weight
+    gradient of every layer and the data gradient of all but the first."""
+    import importlib.util
+
+    from paper_2506_17713_amd.surrogate import ARCH
+
+    spec = importlib.util.spec_from_file_location("bench", ROOT / "bench.py")
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    sizes = {"enc0a": 16, "enc0b": 16, "enc1a": 8, "enc1b": 8, "enc2a": 4, "enc2b": 4, "bota": 2, "botb": 2,
+             "dec2a": 4, "dec2b": 4, "dec1a": 8, "dec1b": 8, "dec0a": 16, "dec0b": 16, "head": 16}
+    fwd = sum(2 * ci * co * 27 * sizes[n] ** 3 for n, ci, co in ARCH)
+    first = 2 * ARCH[0][1] * ARCH[0][2] * 27 * 16 ** 3
+    f = bench.conv_flops(ARCH, 16)
+    assert f["forward"] == fwd
+    assert f["backward"] == 2 * fwd - first
