@@ -85,30 +85,37 @@ def boundary_voxels(solid, count, seed):
     return np.sort(rng.choice(cand, size=min(count, len(cand)), replace=False))
 
 
-def small_sessile(storage, coll="MRT", mode="PHI", val=1.05):
+# tau = 0.8 and a distinct rate per class of moment rows (d'Humieres order)
+MRT_RATES = (1.3, 1.19, 1.4, 1.1, 1.2, 1.1, 1.2, 1.1, 1.2, 1.25, 1.05, 1.25, 1.05, 1.25, 1.25, 1.25,
+             1.98, 1.98, 1.98)
+
+
+def small_sessile(storage, coll="MRT", mode="PHI", val=1.05, rates=False):
     c = inputs.load_coexistence()["CS"]["0.8"]
     shape = (12, 14, 16)
+    extra = dict(tau=(0.8, 0.8), mrt_s=(MRT_RATES, MRT_RATES)) if rates else {}
     w = inputs.Workload("adj_sessile", "D3Q19", shape, collision=coll, storage=storage,
                         eos_T=(c["T"],) * 2, A=(c["A"],) * 2, wet_mode=(mode, mode), wet=(val, val),
-                        rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2)
+                        rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2, **extra)
     solid = inputs.walls(shape, "z", (0, 11))
     rho = inputs.droplet(shape, (8.0, 7.0, 4.0), 4.5, 3, c["rho_l"], c["rho_v"])[None]
     return w, solid, rho
 
 
-@pytest.mark.parametrize("coll,mode,val", [("MRT", "PHI", 1.05), ("BGK", "DRHO", 0.01)])
-def test_adjoint_f64_matches_oracle_complex_step(oracle_mod, coll, mode, val):
-    w, solid, rho = small_sessile("F64", coll, mode, val)
+@pytest.mark.parametrize("coll,mode,val,rates", [("MRT", "PHI", 1.05, False), ("BGK", "DRHO", 0.01, False),
+                                                 ("MRT", "PHI", 1.05, True)])
+def test_adjoint_f64_matches_oracle_complex_step(oracle_mod, coll, mode, val, rates):
+    w, solid, rho = small_sessile("F64", coll, mode, val, rates)
     steps, ckpt = 40, 7
     # wall voxels under and around the droplet
     vox = [(0 * 14 + 7) * 16 + 8, (0 * 14 + 7) * 16 + 12, (0 * 14 + 3) * 16 + 8, (0 * 14 + 10) * 16 + 3,
            (11 * 14 + 7) * 16 + 8]
-    print(f"case adjoint F64 {coll} {mode} {w.shape} {steps} steps", flush=True)
+    print(f"case adjoint F64 {coll} {mode} rates={rates} {w.shape} {steps} steps", flush=True)
     L, g, dT = gpu_grad(w, solid, rho, steps, ckpt)
     S, go, dTo = oracle_cstep(oracle_mod, w, solid, rho, steps, vox)
     rel = np.abs(g[vox] - go).max() / np.abs(go).max()
     relT = abs(dT - dTo) / abs(dTo)
-    _report({"case": f"adjoint_f64_{coll}_{mode}", "L": L, "L_oracle": S, "rel_err_dwet": rel,
+    _report({"case": f"adjoint_f64_{coll}_{mode}{'_rates' if rates else ''}", "L": L, "L_oracle": S, "rel_err_dwet": rel,
              "rel_err_dT": relT, "dwet_oracle": go.tolist(), "dT_oracle": dTo})
     print(L, S, rel, relT, flush=True)
     assert abs(L - S) < 1e-12

@@ -62,10 +62,61 @@ def run_pair(oracle_mod, w, solid, rho, steps, u0=None, wet=None, comps=None):
     rec = {"case": w.name, "lattice": w.lattice, "collision": w.collision, "storage": w.storage,
            "nc": w.nc, "shape": list(w.shape), "steps": steps,
            "err": {str(c): v for c, v in out.items()},
-           "mass_rel_err": [float(abs(st["mass"][k] - mass_ref[k]) / mass_ref[k]) for k in range(w.nc)]}
+           "mass_rel_err": [float(abs(st["mass"][k] - mass_ref[k]) / mass_ref[k]) for k in range(w.nc)],
+           "stats_err": stats_errors(st, fl, w, solid)}
     print(rec, flush=True)
     _report(rec)
+    tol = STATS_TOL.get(w.storage)
+    if tol is not None:
+        for key, v in rec["stats_err"].items():
+            assert v <= tol, (key, v, tol)
     return out, st, rec
+
+
+# Bound on each lbm_stats slot against the same quantity formed from the
+# oracle's fields, as a fraction of its natural scale (see stats_errors).
+# 16-bit storage is reported, not bounded.
+STATS_TOL = {"F64": 1e-10, "F32": 1e-4}
+
+
+def stats_errors(st, fl, w, solid):
+    """Errors of the lbm_stats reduction slots against the oracle's fields
+    after the same steps, each scaled to the size of what it measures:
+      mass[k]      relative to the oracle's mass of component k
+      momentum[d]  relative to sum_fluid rho_tot * max|u_mix|
+      mean_ux      relative to max|u_mix,x|
+      saturation   excess of the disagreement in the classified node count
+                   over the nodes whose class is within 1e-4 of the threshold
+                   in the oracle (those may go either way in FP32), per node.
+    The slot definitions are those of lbm_stats_t: fluid nodes only; the
+    mixture velocity of Eq. 6; non-wetting = rho^0 >= rho^1 (two components)
+    or rho < (rho_min + rho_max) / 2 (one component)."""
+    fluid = solid.reshape(-1) == 0
+    rho = fl["rho"][:, fluid]
+    um = fl["umix"][:, fluid]
+    rt = rho.sum(0)
+    n = fluid.sum()
+    umax = max(np.abs(um).max(), 1e-300)
+    err = {}
+    for k in range(w.nc):
+        m = rho[k].sum()
+        err[f"mass{k}"] = float(abs(st["mass"][k] - m) / m)
+    mom = (rt[None, :] * um).sum(1)
+    scale = rt.sum() * umax
+    for d in range(3):
+        err[f"momentum{d}"] = float(abs(st["momentum"][d] - mom[d]) / scale)
+    err["mean_ux"] = float(abs(st["mean_ux"] - um[0].mean()) / max(np.abs(um[0]).max(), 1e-300))
+    if w.nc > 1:
+        margin = rho[0] - rho[1]
+        nw = margin >= 0
+        amb = np.abs(margin) <= 1e-4 * rho.max()
+    else:
+        mid = 0.5 * (w.rho_min[0] + w.rho_max[0])
+        nw = rho[0] < mid
+        amb = np.abs(rho[0] - mid) <= 1e-4 * rho.max()
+    diff = abs(round(st["saturation"] * n) - int(nw.sum()))
+    err["saturation"] = float(max(0, diff - int(amb.sum())) / n)
+    return err
 
 
 def assert_tol(out, tol):
@@ -162,6 +213,69 @@ def test_droplet_2d_f32(oracle_mod):
     assert_tol(out, 1e-4)
 
 
+# ------------------------------------------------ MRT at non-unit relaxation rates
+# tau = 0.8 (s_nu = 1.25 on the stress rows) and a distinct rate on every other
+# class of moment rows, so that a rate applied to the wrong row changes the
+# result.  D3Q19 rows: rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww,
+# piww, pxy, pyz, pxz, mx, my, mz; D2Q9 rows: rho, e, eps, jx, qx, jy, qy,
+# pxx, pxy.  The conserved rows take 1.3 (rho) and 1.1 (j): with two
+# components and the common velocity u' the momentum rows of f - f^eq are not
+# zero, so their rate acts.
+S_NU = 1.0 / 0.8
+MRT_D3Q19 = (1.3, 1.19, 1.4, 1.1, 1.2, 1.1, 1.2, 1.1, 1.2, S_NU, 1.05, S_NU, 1.05, S_NU, S_NU, S_NU,
+             1.98, 1.98, 1.98)
+MRT_D2Q9 = (1.3, 1.19, 1.4, 1.1, 1.2, 1.1, 1.2, S_NU, S_NU)
+
+
+def _sessile_mrt(storage, shape=(29, 37, 45)):
+    c = inputs.load_coexistence()["CS"]["0.8"]
+    w = inputs.Workload("sessile3d_mrt_rates", "D3Q19", shape, collision="MRT", storage=storage,
+                        tau=(0.8, 0.8), mrt_s=(MRT_D3Q19, MRT_D3Q19), eos_T=(c["T"],) * 2,
+                        A=(c["A"],) * 2, wet_mode=("PHI", "PHI"), wet=(1.1, 1.1),
+                        rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2)
+    solid = inputs.walls(shape, "z", (0, shape[0] - 1))
+    rho = inputs.droplet(shape, (20.0, 18.0, 9.0), 9, 4, c["rho_l"], c["rho_v"])[None]
+    return w, solid, rho
+
+
+@pytest.mark.parametrize("storage,tol", [("F64", 1e-10), ("F32", 1e-4)])
+def test_mrt_nonunit_rates_sessile_3d(oracle_mod, storage, tol):
+    w, solid, rho = _sessile_mrt(storage)
+    out, _, _ = run_pair(oracle_mod, w, solid, rho, 300)
+    assert_tol(out, tol)
+
+
+# Two components with a 3 % trace phase: at tau = 0.8 the trace density is
+# driven negative near the interfaces within 100-200 steps (in the oracle, by
+# BGK as well as by MRT with ghost rates 1.98), after which the per-component
+# velocity j/rho is meaningless.  The ghost rows therefore take 1.5, which
+# keeps the trace density above 0.004 over the run; the other rates are those
+# above.
+MRT_D3Q19_2C = MRT_D3Q19[:16] + (1.5, 1.5, 1.5)
+
+
+@pytest.mark.parametrize("storage,tol", [("F64", 1e-10), ("F32", 1e-4)])
+def test_mrt_nonunit_rates_two_component(oracle_mod, storage, tol):
+    # the two-component MRT path (momentum rows relaxed toward u')
+    w, solid, rho = inputs.two_component_pack(shape=(34, 37, 45), storage=storage, radii=(4.0, 7.0), seed=3)
+    w = w.with_(collision="MRT", tau=(0.8, 0.8), mrt_s=(MRT_D3Q19_2C, MRT_D3Q19_2C))
+    out, _, _ = run_pair(oracle_mod, w, solid, rho, 200)
+    assert_tol(out, tol)
+
+
+def test_mrt_nonunit_rates_d2q9_f64(oracle_mod):
+    c = inputs.load_coexistence()["CS"]["0.7"]
+    shape = (1, 45, 70)
+    w = inputs.Workload("sessile2d_mrt_rates", "D2Q9", shape, collision="MRT", storage="F64",
+                        tau=(0.8, 0.8), mrt_s=(MRT_D2Q9, MRT_D2Q9), eos_T=(c["T"],) * 2,
+                        A=(c["A"],) * 2, wet_mode=("PHI", "PHI"), wet=(1.1, 1.1),
+                        rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2)
+    solid = inputs.walls(shape, "y", (0, 44))
+    rho = inputs.droplet(shape, (35.0, 1.0, 0.0), 14, 4, c["rho_l"], c["rho_v"])[None]
+    out, _, _ = run_pair(oracle_mod, w, solid, rho, 300)
+    assert_tol(out, 1e-10)
+
+
 # ------------------------------------------------------- 16-bit deviation storage
 @pytest.mark.parametrize("storage", ["F16DEV", "BF16DEV"])
 def test_deviation_storage_error_is_reported(oracle_mod, storage):
@@ -225,6 +339,30 @@ def test_sessile_256_sampled_nodes_vs_oracle_crops(oracle_mod):
              "max_u_err_rel_1e-3": float(e[:, 1].max())})
     assert e[:, 0].max() < 1e-5
     assert e[:, 1].max() < 1e-3
+
+
+def test_stats_residual_vs_oracle(oracle_mod):
+    """The residual slot, sum|u_x(t) - u_x(t')| / sum|u_x(t)| over fluid nodes
+    between two reductions, against the oracle's mixture velocity at the same
+    two times (FP64, sessile droplet in a ragged domain)."""
+    from paper_2506_17713_amd import lbm
+
+    w, solid, rho = _sessile_mrt("F64", shape=(24, 30, 37))
+    sol = lbm.Solver(w, solid, rho)
+    sol.step(40)
+    sol.stats()
+    sol.step(25)
+    s2 = sol.stats()
+    sol.close()
+    ref = oracle_mod.State(w, solid, rho)
+    ref.step(40)
+    fluid = solid.reshape(-1) == 0
+    ux1 = ref.fields()["umix"][0][fluid]
+    ref.step(25)
+    ux2 = ref.fields()["umix"][0][fluid]
+    r_ref = np.abs(ux2 - ux1).sum() / np.abs(ux2).sum()
+    _report({"case": "stats_residual", "residual": s2["residual"], "residual_oracle": float(r_ref)})
+    assert abs(s2["residual"] - r_ref) <= 1e-10 * r_ref
 
 
 # ------------------------------------------------------ determinism and resume

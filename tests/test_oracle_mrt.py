@@ -180,3 +180,33 @@ def test_d2q9_diagonal_shear_wave_decays_at_nu(oracle_mod):
     r = rates_d2q9()
     r[7] = 1.0
     assert abs(shear_wave_viscosity(oracle_mod, "D2Q9", ("x", "y"), r) / NU - 1.0) > 0.3
+
+
+# rates of the GPU parity cases at non-unit rates (tests/test_gpu_parity.py)
+RATES_GPU = (1.3, 1.19, 1.4, 1.1, 1.2, 1.1, 1.2, 1.1, 1.2, 1.25, 1.05, 1.25, 1.05, 1.25, 1.25, 1.25,
+             1.98, 1.98, 1.98)
+
+
+def test_mrt_rates_change_the_result(oracle_mod):
+    """The non-unit rates of the GPU parity cases are not inert on a sessile
+    droplet: changing the rate of any class of rows moves the oracle's result,
+    so matching the oracle at these rates constrains where each rate acts."""
+    c = inputs.load_coexistence()["CS"]["0.8"]
+    shape = (16, 18, 20)
+    w = Workload("sessile3d_mrt_rates", "D3Q19", shape, collision="MRT", storage="F64",
+                 tau=(0.8, 0.8), mrt_s=(RATES_GPU, RATES_GPU), eos_T=(c["T"],) * 2,
+                 A=(c["A"],) * 2, wet_mode=("PHI", "PHI"), wet=(1.1, 1.1),
+                 rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2)
+    solid = inputs.walls(shape, "z", (0, shape[0] - 1))
+    rho = inputs.droplet(shape, (10.0, 9.0, 6.0), 5, 3, c["rho_l"], c["rho_v"])[None]
+    base = oracle_mod.State(w, solid, rho)
+    base.step(30)
+    r0 = base.fields()["rho"][0]
+    for rows in ((1,), (2,), (4, 6, 8), (9, 11), (10, 12), (13, 14, 15), (16, 17, 18)):
+        s = list(RATES_GPU)
+        for m in rows:
+            s[m] = 1.0 if abs(s[m] - 1.0) > 1e-9 else 1.5
+        st = oracle_mod.State(w.with_(mrt_s=(tuple(s), tuple(s))), solid, rho)
+        st.step(30)
+        d = np.abs(st.fields()["rho"][0] - r0).max() / np.abs(r0).max()
+        assert d > 1e-9, rows
