@@ -43,7 +43,7 @@ def parse():
                     help="sessile: D3Q19 MRT sessile droplet (the headline line); droplet2d: D2Q9 BGK FP64 "
                          "droplet; pack2: D3Q19 two-component sphere pack; adjoint: gradient of the "
                          "saturation over 1000 steps of the 128^3 pack (checkpoint every 100)")
-    ap.add_argument("--storage", default="F32", choices=["F32", "F64", "F16DEV", "BF16DEV"])
+    ap.add_argument("--storage", default="F32", choices=["F32", "F64", "F32F64", "F16DEV", "BF16DEV"])
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -297,7 +297,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds, args.workload)
-    dtype = {"F32": "f32", "F64": "f64", "F16DEV": "f16dev+f32", "BF16DEV": "bf16dev+f32"}[w.storage]
+    dtype = {"F32": "f32", "F64": "f64", "F32F64": "f32 storage, f64 arithmetic", "F16DEV": "f16dev+f32",
+             "BF16DEV": "bf16dev+f32"}[w.storage]
     lat = "D2Q9" if args.workload == "droplet2d" else "D3Q19"
     line = {
         "metric": f"MLUPS of fused {lat} Shan-Chen step (% HBM roofline)",

@@ -23,8 +23,8 @@
  *   - A handle is bound to the stream given to lbm_init; calls on one handle
  *     are not thread-safe.  Work is enqueued asynchronously unless a function
  *     says it synchronises.
- *   - The compute type is double for LBM_STORE_F64 and float otherwise;
- *     "compute-type" buffers below use it.
+ *   - The compute type is double for LBM_STORE_F64 and LBM_STORE_F32_F64 and
+ *     float otherwise; "compute-type" buffers below use it.
  */
 #ifndef PAPER_2506_17713_LBM_H
 #define PAPER_2506_17713_LBM_H
@@ -47,10 +47,14 @@ typedef enum lbm_error {
 
 enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 enum { LBM_BGK = 0, LBM_MRT = 1 };
-/* Population storage.  F64 / F32 store f_i.  F16DEV / BF16DEV store the
- * relative deviation h_i = f_i / (w_i rho*) - 1 in 16 bits plus the node's
- * density rho* in FP32, and reconstruct f_i = w_i rho* (1 + h_i) in FP32. */
-enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16DEV = 2, LBM_STORE_BF16DEV = 3 };
+/* Population storage.  F64 / F32 store f_i and compute in the same type.
+ * F32_F64 stores f_i in FP32 and computes in FP64: the memory and HBM
+ * traffic of FP32 with the accuracy that FP32 rounding of the stored state
+ * alone allows (long runs in FP32 arithmetic accumulate several times that).
+ * F16DEV / BF16DEV store the relative deviation h_i = f_i / (w_i rho*) - 1 in
+ * 16 bits plus the node's density rho* in FP32, and reconstruct
+ * f_i = w_i rho* (1 + h_i) in FP32. */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16DEV = 2, LBM_STORE_BF16DEV = 3, LBM_STORE_F32_F64 = 4 };
 /* Pseudopotential: Carnahan-Starling EOS (Eq. 12) or psi = rho. */
 enum { LBM_PSI_CS = 0, LBM_PSI_DENSITY = 1 };
 /* Improved virtual density (Eq. 17): rho_s = phi rho_ave or rho_ave - drho. */
@@ -159,8 +163,7 @@ int lbm_sync(lbm_handle* h);
 /* Restart from f = f^eq(rho0, u0) (Eq. 3 with the moments given), as
  * lbm_init does, but from device arrays: for callers whose initial fields
  * are computed on the GPU (a learned warm start).  rho0_dev [n_comp][N] and
- * u0_dev [3][N] (NULL: rest) are device arrays of the compute type (double
- * for LBM_STORE_F64, float otherwise), node order as in lbm_init; values at
+ * u0_dev [3][N] (NULL: rest) are device arrays of the compute type, node order as in lbm_init; values at
  * solid nodes are ignored.  Unlike lbm_init the values are not validated: a
  * non-finite or negative density is reported by the next check.  The step
  * counter and the residual history restart; mask, parameters and wetting
@@ -190,7 +193,8 @@ int lbm_set_state(lbm_handle* h, const void* dev_src);
  *                       array dL_drho[N] of the compute type (any objective
  *                       linearised in the final density).
  * Supported for one component with LBM_STORE_F32 or LBM_STORE_F64; other
- * configurations return LBM_ERR_UNSUPPORTED.
+ * configurations (two components, 16-bit storage, LBM_STORE_F32_F64) return
+ * LBM_ERR_UNSUPPORTED.
  * ------------------------------------------------------------------------ */
 enum { LBM_OBS_SATURATION = 0, LBM_OBS_DRHO = 1 };
 

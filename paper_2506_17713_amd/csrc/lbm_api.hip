@@ -45,7 +45,7 @@ int validate(const lbm_params* p) {
     if ((long long)p->nx * (p->lattice == LBM_D2Q9 ? 1 : p->ny) >= (1LL << 29)) return LBM_ERR_ARG;
     if (p->n_comp < 1 || p->n_comp > 2) return LBM_ERR_ARG;
     if (p->collision != LBM_BGK && p->collision != LBM_MRT) return LBM_ERR_ARG;
-    if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_BF16DEV) return LBM_ERR_ARG;
+    if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F32_F64) return LBM_ERR_ARG;
     if (p->check_every < 0) return LBM_ERR_ARG;
     for (int i = 0; i < 4; ++i)
         if (p->reserved[i] != 0) return LBM_ERR_ARG;
@@ -169,7 +169,7 @@ void fill_args(lbm_handle* h, StepArgs<R>& a, const Buffers* bufs) {
 template <int LAT, int NC, int ST, int COLL, bool MOM>
 constexpr int tile_b() {
     if (LAT == LAT_D2Q9) return 1;
-    if (ST == ST_F64) return 4;
+    if (ST == ST_F64 || ST == ST_F32D) return 4;
     constexpr bool dev = ST == ST_F16 || ST == ST_BF16;
     if (COLL == COLL_BGK && !MOM && ((NC == 1 && ST == ST_F32) || (NC == 2 && dev))) return LBM_TILE_B_BGK;
     return LBM_TILE_B;
@@ -199,7 +199,7 @@ hipError_t launch_step(lbm_handle* h, StepArgs<typename Store<ST>::R>& a) {
     const int nblk = tiles * nchunks;
     // own-node populations stay in registers between pull and collision
     // where three sets fit (one component, 32-bit arithmetic)
-    constexpr bool CARRY = LBM_CARRY && NC == 1 && ST != ST_F64;
+    constexpr bool CARRY = LBM_CARRY && NC == 1 && ST != ST_F64 && ST != ST_F32D;
     hipLaunchKernelGGL((k_step<LAT, NC, ST, COLL, MOM, TA, TB, CARRY>), dim3(nblk), dim3(TA * TB), 0,
                        h->stream, a);
     return hipGetLastError();
@@ -230,6 +230,14 @@ hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u,
             a.mom_rho = (float*)rho;
             a.mom_u = (float*)u;
             return dispatch_coll<LAT, NC, ST_F32>(h, mom, a);
+        }
+        case LBM_STORE_F32_F64: {
+            StepArgs<double> a;
+            fill_args(h, a, bufs);
+            a.mom_comp = comp;
+            a.mom_rho = (double*)rho;
+            a.mom_u = (double*)u;
+            return dispatch_coll<LAT, NC, ST_F32D>(h, mom, a);
         }
         case LBM_STORE_F16DEV: {
             StepArgs<float> a;
@@ -347,7 +355,7 @@ hipError_t enqueue_stats(lbm_handle* h) {
     const double mid = 0.5 * (h->p.rho_min[0] + h->p.rho_max[0]);
     const uint32_t* nbr = reinterpret_cast<const uint32_t*>(ws + h->lay.nbr);
     double* part = reinterpret_cast<double*>(ws + h->lay.partial);
-    if (h->p.storage == LBM_STORE_F64) {
+    if (real_bytes(h->p.storage) == 8) {
         hipLaunchKernelGGL(k_reduce1<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream,
                            reinterpret_cast<const double*>(ws + h->lay.mrho),
                            reinterpret_cast<const double*>(ws + h->lay.mu),
@@ -392,6 +400,7 @@ hipError_t init_store(lbm_handle* h, const void* rho0, const void* u0) {
     switch (h->p.storage) {
         case LBM_STORE_F64: return launch_init<LAT, NC, ST_F64>(h, rho0, u0);
         case LBM_STORE_F32: return launch_init<LAT, NC, ST_F32>(h, rho0, u0);
+        case LBM_STORE_F32_F64: return launch_init<LAT, NC, ST_F32D>(h, rho0, u0);
         case LBM_STORE_F16DEV: return launch_init<LAT, NC, ST_F16>(h, rho0, u0);
         default: return launch_init<LAT, NC, ST_BF16>(h, rho0, u0);
     }

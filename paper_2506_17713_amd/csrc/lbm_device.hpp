@@ -30,7 +30,7 @@ namespace lbm {
 
 enum { LAT_D2Q9 = 0, LAT_D3Q19 = 1 };
 enum { COLL_BGK = 0, COLL_MRT = 1 };
-enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32D = 4 };
 
 // ---------------------------------------------------------------------------
 // Compile-time iteration.
@@ -288,6 +288,12 @@ template <> struct Store<ST_F64> {
 template <> struct Store<ST_F32> {
     using S = float;
     using R = float;
+    static constexpr bool DEV = false;
+};
+// FP32 populations, FP64 arithmetic (values widen on load, round on store)
+template <> struct Store<ST_F32D> {
+    using S = float;
+    using R = double;
     static constexpr bool DEV = false;
 };
 template <> struct Store<ST_F16> {
@@ -747,14 +753,21 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
         if constexpr (RSR) rs_fetch(cp + 2, rsn);
         Pull<LAT, ST, NC, (NC > 1), RSR> po;
         Pull<LAT, ST, NC, (NC > 1), RSR> ph[OVERLAP ? HPT : 1];
-        po.issue(P, own_a, own_b, c, wo);
+        // A solid node holds no populations: its lane issues no loads (a
+        // wavefront of solid nodes skips the pull), and its registers are
+        // never read, since the ring marks it solid and its collision returns.
+        // (two components only: with one component the branch would split the
+        // overlapped own-node and halo loads, which costs more than the few
+        // solid lanes of its workloads save)
+        const bool own_fluid = NC == 1 || !(wo & 1u);
+        if (own_fluid) po.issue(P, own_a, own_b, c, wo);
         if constexpr (OVERLAP) {
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
                 if (need(j)) ph[j].issue(P, h_a[j], h_b[j], c, wh[j]);
         }
         if constexpr (RSR) rs_store(cp + 2, rsn);
-        po.finish(P, own_a, own_b, c, wo, fo);
+        if (own_fluid) po.finish(P, own_a, own_b, c, wo, fo);
         if constexpr (RSR)
             if (!(wo & 1u)) rs_scale(fo, wo, (lb_own + 3) * SWA + la_own + 3, cp);
         if (wo & 1u) {
@@ -1012,43 +1025,57 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
                 const R dx = F[k][0] * invr, dy = F[k][1] * invr, dz = F[k][2] * invr;
                 const R usq = (R)1.5 * (ux * ux + uy * uy + uz * uz);
                 const R dsq = (R)1.5 * ((R)2 * (ux * dx + uy * dy + uz * dz) + dx * dx + dy * dy + dz * dz);
-                const R r1u = r * ((R)1 - usq);
                 // Opposite directions i, i+1 (e_{i+1} = -e_i) share the even part
                 // of f^eq and of the forcing term and negate the odd part:
                 //   f^eq_i     = w rho (1 + 4.5 (e.u)^2 - 1.5 u^2) +- 3 w rho e.u
                 //   dF_i (Eq. 5) = f^eq_i(rho, u + du) - f^eq_i(rho, u)
                 //              = w rho (4.5 e.du (2 e.u + e.du) - 1.5 (2 u.du + du^2)) +- 3 w rho e.du
-                // (expanded so that no two O(w rho) numbers are subtracted).
+                // (expanded so that no two O(w rho) numbers are subtracted).  Every
+                // term is formed as w rho times a bracket that holds only the
+                // velocity-dependent part, and w rho (one product per weight class)
+                // enters once, through a fused multiply-add: in single precision a
+                // population then carries two roundings at its own magnitude instead
+                // of four to seven, which is what limits the accuracy of long runs
+                // whose slow modes integrate the per-step rounding.
+                [[maybe_unused]] const R wr0 = (R)L::w(0) * r;  // rest
+                const R wrA = (R)L::w(1) * r;                 // class of direction 1
+                const R wrB = (R)L::w(Q - 1) * r;             // the other class
+                auto wr_of = [&](auto PI) -> R {
+                    return pair_in<LAT>(decltype(PI)::value, 0) ? wrA : wrB;
+                };
                 // even / odd parts of f^eq (q) and of the forcing term (g) of pair p
                 auto eq_parts = [&](auto PI, R& qs, R& qa) {
                     constexpr int i = 2 * decltype(PI)::value + 1;
-                    constexpr R w = (R)L::w(i);
+                    const R wr = wr_of(PI);
                     const R eu = dot_e<L::ex[i], L::ey[i], L::ez[i]>(ux, uy, uz);
-                    qs = w * r1u + ((R)4.5 * w * r) * (eu * eu);
-                    qa = ((R)3 * w * r) * eu;
+                    qs = wr + wr * ((R)4.5 * (eu * eu) - usq);
+                    qa = wr * ((R)3 * eu);
                 };
                 auto force_parts = [&](auto PI, R& gs, R& ga) {
                     constexpr int i = 2 * decltype(PI)::value + 1;
-                    constexpr R w = (R)L::w(i);
+                    const R wr = wr_of(PI);
                     const R eu = dot_e<L::ex[i], L::ey[i], L::ez[i]>(ux, uy, uz);
                     const R ed = dot_e<L::ex[i], L::ey[i], L::ez[i]>(dx, dy, dz);
-                    gs = (w * r) * ((R)4.5 * ed * ((R)2 * eu + ed) - dsq);
-                    ga = ((R)3 * w * r) * ed;
+                    gs = wr * ((R)4.5 * ed * ((R)2 * eu + ed) - dsq);
+                    ga = wr * ((R)3 * ed);
                 };
                 R fo[Q];
                 if constexpr (COLL == COLL_BGK) {
-                    // f* = f - omega (f - f^eq) + dF
+                    // f* = (1 - omega) f + omega f^eq + dF
+                    //    = (1 - omega) f + omega w rho + w rho (s_even +- s_odd)
                     const R om = P.omega[k], om1 = (R)1 - om;
+                    const R woA = om * wrA, woB = om * wrB;
                     sfor<NP>([&](auto PI) {
                         constexpr int p = decltype(PI)::value;
                         constexpr int i = 2 * p + 1;
-                        R qs, qa, fs, fa;
-                        eq_parts(PI, qs, qa);
-                        force_parts(PI, fs, fa);
-                        const R gs = om * qs + fs;
-                        const R ga = om * qa + fa;
-                        fo[i] = om1 * f[k][i] + (gs + ga);
-                        fo[i + 1] = om1 * f[k][i + 1] + (gs - ga);
+                        const R wr = wr_of(PI);
+                        const R wo = pair_in<LAT>(p, 0) ? woA : woB;
+                        const R eu = dot_e<L::ex[i], L::ey[i], L::ez[i]>(ux, uy, uz);
+                        const R ed = dot_e<L::ex[i], L::ey[i], L::ez[i]>(dx, dy, dz);
+                        const R se = om * ((R)4.5 * (eu * eu) - usq) + ((R)4.5 * ed * ((R)2 * eu + ed) - dsq);
+                        const R so = (R)3 * (om * eu + ed);
+                        fo[i] = om1 * f[k][i] + (wo + wr * (se + so));
+                        fo[i + 1] = om1 * f[k][i + 1] + (wo + wr * (se - so));
                     });
                 } else {
                     // f* = f - M^-1 S M (f - f^eq) + dF with M^-1 = M^T diag(1/|row|^2)
@@ -1065,7 +1092,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
                         dp[p] = (f[k][i] + f[k][i + 1]) - (R)2 * qs;
                         dm[p] = (f[k][i] - f[k][i + 1]) - (R)2 * qa;
                     });
-                    const R d0 = f[k][0] - (R)L::w(0) * r1u;
+                    const R d0 = f[k][0] - (wr0 - wr0 * usq);
                     if constexpr (LAT == LAT_D3Q19) {
                         R sr[19], E[NP], O[NP];
 #pragma unroll

@@ -23,8 +23,10 @@ struct Layout {
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 inline int q_of(int lat) { return lat == LBM_D2Q9 ? 9 : 19; }
-inline size_t store_bytes(int st) { return st == LBM_STORE_F64 ? 8 : (st == LBM_STORE_F32 ? 4 : 2); }
-inline size_t real_bytes(int st) { return st == LBM_STORE_F64 ? 8 : 4; }
+inline size_t store_bytes(int st) {
+    return st == LBM_STORE_F64 ? 8 : ((st == LBM_STORE_F32 || st == LBM_STORE_F32_F64) ? 4 : 2);
+}
+inline size_t real_bytes(int st) { return (st == LBM_STORE_F64 || st == LBM_STORE_F32_F64) ? 8 : 4; }
 inline bool is_dev(int st) { return st == LBM_STORE_F16DEV || st == LBM_STORE_BF16DEV; }
 
 // Explicit population buffers for one launch of the fused step.

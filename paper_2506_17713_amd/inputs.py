@@ -47,7 +47,7 @@ class Workload:
     shape: tuple                      # (nz, ny, nx)
     nc: int = 1
     collision: str = "BGK"            # "BGK" or "MRT"
-    storage: str = "F32"              # "F64", "F32", "F16DEV", "BF16DEV"
+    storage: str = "F32"              # "F64", "F32", "F32F64", "F16DEV", "BF16DEV"
     tau: tuple = (1.0, 1.0)
     mrt_s: tuple | None = None        # explicit rates per component, else defaults
     psi_kind: tuple = ("CS", "CS")    # "CS" (Carnahan-Starling EOS) or "DENSITY"
@@ -98,6 +98,15 @@ class Workload:
 
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
+
+
+def dhumieres_rates(tau: float) -> tuple:
+    """D3Q19 MRT rates of d'Humieres et al. (2002) in the row order of
+    Workload.mrt_rates: s_nu = 1/tau on the stress rows (3p_xx, p_ww, p_xy,
+    p_yz, p_xz) and on the conserved rows (where m - m^eq vanishes for one
+    component), s_e = 1.19, s_eps = 1.4, s_q = 1.2, s_pi = 1.4, s_m = 1.98."""
+    sv = 1.0 / tau
+    return (sv, 1.19, 1.4, sv, 1.2, sv, 1.2, sv, 1.2, sv, 1.4, sv, 1.4, sv, sv, sv, 1.98, 1.98, 1.98)
 
 
 # --------------------------------------------------------------------------
@@ -200,12 +209,15 @@ def droplet_2d(n=128, steps=2000, storage="F64", r=20.0, w=5.0, tr=0.7, seed=0, 
 def sessile_3d(n=256, steps=20000, storage="F32", r=30.0, w=5.0, tr=0.8, wet_mode="PHI",
                wet=1.0, collision="MRT", nxy=None, center=None):
     """D3Q19 Carnahan-Starling droplet resting on a solid wall at z = 0 (and a
-    second wall at z = nz-1); x and y periodic."""
+    second wall at z = nz-1); x and y periodic.  MRT takes the d'Humieres
+    rates at tau = 1 (with tau = 1 and every other rate 1 it would reduce to
+    BGK)."""
     T, rv, rl, A = _cs(tr)
     nx = ny = nxy or n
     shape = (n, ny, nx)
+    dh = dhumieres_rates(1.0)
     wl = Workload("sessile3d", "D3Q19", shape, storage=storage, collision=collision,
-                  tau=(1.0, 1.0), eos_T=(T, T), A=(A, A), wet_mode=(wet_mode, wet_mode),
+                  tau=(1.0, 1.0), mrt_s=(dh, dh), eos_T=(T, T), A=(A, A), wet_mode=(wet_mode, wet_mode),
                   wet=(wet, wet), rho_min=(rv, rv), rho_max=(rl, rl), steps=steps)
     solid = walls(shape, "z", (0, n - 1))
     c = center or (nx / 2, ny / 2, r + 1.0)
@@ -243,15 +255,17 @@ def two_component_pack(n=400, steps=100, storage="F32", seed=0, porosity=0.35, r
 def adjoint_pack(n=128, steps=1000, storage="F32", seed=1, porosity=0.4, radii=(6.0, 14.0),
                  tr=0.8, phi=1.2, w=5.0, collision="MRT", shape=None, solid=None):
     """D3Q19 single-component CS at T_r = 0.8 in a periodic sphere pack; liquid
-    slab x < nx/2, vapour elsewhere; uniform wetting phi."""
+    slab x < nx/2, vapour elsewhere; uniform wetting phi; MRT with the
+    d'Humieres rates at tau = 1, as the sessile droplet."""
     T, rv, rl, A = _cs(tr)
     shape = shape or (n, n, n)
     nz, ny, nx = shape
     if solid is None:
         solid = sphere_pack(shape, radii, porosity, seed)
     rho = slab(shape, "x", 0, nx // 2, w, rl, rv)
+    dh = dhumieres_rates(1.0)
     wl = Workload("adjoint_pack", "D3Q19", tuple(shape), storage=storage, collision=collision,
-                  tau=(1.0, 1.0), eos_T=(T, T), A=(A, A), wet_mode=("PHI", "PHI"),
+                  tau=(1.0, 1.0), mrt_s=(dh, dh), eos_T=(T, T), A=(A, A), wet_mode=("PHI", "PHI"),
                   wet=(phi, phi), rho_min=(rv, rv), rho_max=(rl, rl), steps=steps)
     return wl, solid, rho[None]
 

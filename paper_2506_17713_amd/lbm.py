@@ -18,7 +18,7 @@ LIB_PATH = HERE / "_lib" / "liblbm.so"
 LBM_OK = 0
 ERRORS = {-1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP", -4: "LBM_ERR_NONFINITE",
           -5: "LBM_ERR_SPACE"}
-STORAGE = {"F64": 0, "F32": 1, "F16DEV": 2, "BF16DEV": 3}
+STORAGE = {"F64": 0, "F32": 1, "F16DEV": 2, "BF16DEV": 3, "F32F64": 4}
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_moments", "lbm_stats", "lbm_sync",
            "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_reset", "lbm_grad_workspace_size", "lbm_grad",
            "lbm_free", "lbm_strerror"]
@@ -165,7 +165,7 @@ class Solver:
                                self.ws.data_ptr(), size.value, self.stream.cuda_stream, C.byref(h))
         _check("lbm_init", rc)
         self.h = h
-        self.real = torch.float64 if w.storage == "F64" else torch.float32
+        self.real = torch.float64 if w.storage in ("F64", "F32F64") else torch.float32
 
     # -- stepping and observation -------------------------------------------
     def step(self, n: int = 1) -> None:
