@@ -15,7 +15,8 @@
  *   3. pseudopotential psi^k and U^k from the EOS               (Eq. 12)
  *   4. Shan-Chen / Zhang-Chen interaction force + body force     (Eq. 13)
  *   5. equilibrium velocity (bare j/rho; common velocity for two components)
- *   6. BGK or MRT collision, then exact-difference forcing      (Eq. 3, Eq. 5)
+ *   6. BGK or MRT collision, then exact-difference forcing      (Eq. 3, Eq. 5);
+ *      D2Q9 MRT optionally with the surface-tension source C    (Eq. 14-16)
  *   7. streaming with halfway bounce-back at solid nodes        (Eq. 2)
  * Macroscopic velocity output uses the half-force correction   (Eq. 6).
  *
@@ -68,6 +69,7 @@ typedef struct {
     double g[MAXC][MAXC];              /* interaction strengths g_kk'         */
     double body[3];                    /* body acceleration                   */
     double rho_min[MAXC], rho_max[MAXC]; /* virtual-density limiter bounds    */
+    double kappa[MAXC];                /* surface-tension adjustment (D2Q9 MRT) */
 } oref_params;
 
 /* ------------------------------------------------------------------------ */
@@ -282,6 +284,7 @@ typedef struct {
     real_t *psi;     /* [nc][N] */
     real_t *U;       /* [nc][N] */
     real_t *F;       /* [nc][3][N] total force on component k */
+    real_t *Q;       /* [nc][3][N] Q_xx, Q_yy, Q_xy of Eq. 16 (D2Q9 with kappa) */
     uint8_t *active; /* solid node with at least one fluid neighbour */
 } work_t;
 
@@ -293,8 +296,9 @@ static int work_alloc(const oref_params *p, long N, work_t *W)
     W->psi = (real_t *)calloc((size_t)nc * N, sizeof(real_t));
     W->U = (real_t *)calloc((size_t)nc * N, sizeof(real_t));
     W->F = (real_t *)calloc((size_t)nc * 3 * N, sizeof(real_t));
+    W->Q = (real_t *)calloc((size_t)nc * 3 * N, sizeof(real_t));
     W->active = (uint8_t *)calloc((size_t)N, 1);
-    if (!W->rho || !W->j || !W->psi || !W->U || !W->F || !W->active) return -1;
+    if (!W->rho || !W->j || !W->psi || !W->U || !W->F || !W->Q || !W->active) return -1;
     return 0;
 }
 
@@ -305,6 +309,7 @@ static void work_free(work_t *W)
     free(W->psi);
     free(W->U);
     free(W->F);
+    free(W->Q);
     free(W->active);
 }
 
@@ -398,6 +403,46 @@ static void fields(const oref_params *p, const geom_t *G, const uint8_t *solid,
             }
             for (int d = 0; d < 3; ++d) W->F[((long)k * 3 + d) * N + n] = Fk[d];
         }
+
+    /* 4b. Tensor Q of the surface-tension source (Eq. 16) at fluid nodes, for
+     * components with kappa != 0 (D2Q9 only):
+     *   Q = kappa g_kk [ (1 - A) psi(x) sum_i G_i (psi(x+e_i) - psi(x)) e_i e_i
+     *                   + (A/2) sum_i G_i (psi(x+e_i)^2 - psi(x)^2) e_i e_i ]
+     * with the force stencil G_i = w_i / c_s^2.  The printed Eq. 16 leaves out
+     * the interaction strength; with the factor g_kk the surface tension
+     * falls with kappa as Table 2 prints it (0.457 of its unmodified value at
+     * 1 - kappa = 0.5, about 0.01 at 1 - kappa = 0.01), and the coexistence
+     * densities stay put (Table 1). */
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n)
+        for (int k = 0; k < nc; ++k) {
+            real_t Qxx = 0.0, Qyy = 0.0, Qxy = 0.0;
+            if (p->kappa[k] != 0.0 && !solid[n]) {
+                real_t ps = W->psi[(long)k * N + n];
+                real_t s_xx = 0.0, s_yy = 0.0, s_xy = 0.0, t_xx = 0.0, t_yy = 0.0, t_xy = 0.0;
+                for (int i = 1; i < q; ++i) {
+                    int m = G->nbr[i * N + n];
+                    double Gi = 3.0 * L->w[i];
+                    real_t pm = W->psi[(long)k * N + m];
+                    real_t a = Gi * (pm - ps), b = Gi * (pm * pm - ps * ps);
+                    double ex = L->e[i][0], ey = L->e[i][1];
+                    s_xx += a * ex * ex;
+                    s_yy += a * ey * ey;
+                    s_xy += a * ex * ey;
+                    t_xx += b * ex * ex;
+                    t_yy += b * ey * ey;
+                    t_xy += b * ex * ey;
+                }
+                double c = p->kappa[k] * p->g[k][k];
+                double A = p->A[k];
+                Qxx = c * ((1.0 - A) * ps * s_xx + 0.5 * A * t_xx);
+                Qyy = c * ((1.0 - A) * ps * s_yy + 0.5 * A * t_yy);
+                Qxy = c * ((1.0 - A) * ps * s_xy + 0.5 * A * t_xy);
+            }
+            W->Q[((long)k * 3 + 0) * N + n] = Qxx;
+            W->Q[((long)k * 3 + 1) * N + n] = Qyy;
+            W->Q[((long)k * 3 + 2) * N + n] = Qxy;
+        }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -446,6 +491,18 @@ static void collide(const oref_params *p, const geom_t *G, const uint8_t *solid,
                     real_t s = 0.0;
                     for (int i = 0; i < q; ++i) s += M[a][i] * (fi[i] - fe[i]);
                     m[a] = p->mrt_s[k][a] * s;
+                }
+                /* surface-tension source in moment space (Eq. 15, D2Q9 rows
+                 * rho, e, eps, jx, qx, jy, qy, pxx, pxy), added after the
+                 * relaxation: f* = f - M^-1 (S(m - m^eq) - C) */
+                if (p->kappa[k] != 0.0) {
+                    real_t Qxx = W->Q[((long)k * 3 + 0) * N + n];
+                    real_t Qyy = W->Q[((long)k * 3 + 1) * N + n];
+                    real_t Qxy = W->Q[((long)k * 3 + 2) * N + n];
+                    m[1] -= 1.5 * p->mrt_s[k][1] * (Qxx + Qyy);
+                    m[2] -= -1.5 * p->mrt_s[k][2] * (Qxx + Qyy);
+                    m[7] -= -p->mrt_s[k][7] * (Qxx - Qyy);
+                    m[8] -= -p->mrt_s[k][8] * Qxy;
                 }
                 for (int i = 0; i < q; ++i) {
                     real_t s = 0.0;
@@ -597,6 +654,8 @@ int API(step)(const oref_params *p, const uint8_t *solid, const real_t *wet, rea
     work_t W;
     double M[MAXQ][MAXQ], Mi[MAXQ][MAXQ];
     if (p->nc < 1 || p->nc > MAXC) return -1;
+    for (int k = 0; k < p->nc; ++k)
+        if (p->kappa[k] != 0.0 && (p->lattice != 0 || p->collision != 1)) return -4;
     if (geom_init(p, &G)) return -2;
     build_mrt(&G.L, M);
     if (invert(G.L.q, M, Mi)) return -3;

@@ -55,6 +55,7 @@ class OrefParams(C.Structure):
         ("g", (C.c_double * MAXC) * MAXC),
         ("body", C.c_double * 3),
         ("rho_min", C.c_double * MAXC), ("rho_max", C.c_double * MAXC),
+        ("kappa", C.c_double * MAXC),
     ]
 
 
@@ -96,6 +97,7 @@ def params_from(w, T_im: float | tuple = 0.0) -> OrefParams:
         for kk in range(w.nc):
             p.g[k][kk] = w.g[k][kk]
         p.rho_min[k], p.rho_max[k] = w.rho_min[k], w.rho_max[k]
+        p.kappa[k] = w.kappa[k]
     for d in range(3):
         p.body[d] = w.body[d]
     return p

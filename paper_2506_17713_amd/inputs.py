@@ -64,6 +64,7 @@ class Workload:
     rho_min: tuple = (0.0, 0.0)
     rho_max: tuple = (1e30, 1e30)
     common_velocity: bool = True
+    kappa: tuple = (0.0, 0.0)         # surface-tension adjustment (D2Q9 MRT, Eq. 14-16)
     steps: int = 100
     extra: dict = field(default_factory=dict)
 
