@@ -60,6 +60,18 @@ int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, in
  * (64 chunks per channel, then the chunk sums in order).  scratch: device
  * double[64 c].  Errors: LBM_ERR_ARG (c < 1, c > 65535, P < 1, NULL), LBM_ERR_HIP. */
 int lbm_nn_bias_grad(const float* dY, int c, int64_t P, float* db, double* scratch, void* stream);
+/* lbm_nn_bias_grad without the scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid allocation).  The chunk partials live
+ * in a library-owned device array of 64 x 1024 doubles (512 KiB), one per
+ * device, held until the process ends; the call itself allocates nothing.
+ * Same result, bit for bit, as lbm_nn_bias_grad.  c must be <= 1024
+ * (LBM_ERR_ARG otherwise).  All calls on one device share that array: calls
+ * that overlap in time on one device (different streams or threads) race;
+ * calls ordered on one stream do not.  Each call rewrites every partial it
+ * reads, so nothing carries over between calls.
+ * Errors: LBM_ERR_ARG (c < 1, c > 1024, P < 1, NULL), LBM_ERR_HIP. */
+int lbm_nn_bias_grad_noalloc(const float* dY, int c, int64_t P, float* db, void* stream);
 /* dY[i] *= (Y[i] > 0) */
 int lbm_nn_relu_bwd(const float* Y, float* dY, int64_t n, void* stream);
 /* y[i] += x[i] */

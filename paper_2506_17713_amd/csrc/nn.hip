@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "lbm.h"
 #include "lbm_nn.h"
@@ -415,7 +416,33 @@ inline int ok(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_HIP; }
 
 int wgrad_chunks(int64_t P) { return P >= 65536 ? 64 : (P >= 4096 ? 8 : 1); }
 
+constexpr int kBiasNoallocMaxC = 1024;
+constexpr int kMaxDevices = 64;
+
 }  // namespace
+
+// Library-owned scratch of lbm_nn_bias_grad_noalloc: the chunk partial sums
+// of up to kBiasNoallocMaxC channels (512 KiB), one copy per device for the
+// life of the process.  Host code never passes the symbol itself to a kernel
+// (in host code it names a host-side stand-in); it uses the device address
+// that hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) double scratch[kBiasChunks * kBiasNoallocMaxC];
+static double* g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+static int bias_scratch_ptr(double** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LBM_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LBM_ERR_HIP;
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return LBM_OK;
+}
+
 
 // Symmetry transform of a field X [C][D][H][W] (training-set augmentation):
 // Y[c](r) = sign[c] * X[src[c]](g^-1 r) with g = periodic shift o axis flips o
@@ -536,6 +563,17 @@ int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, in
 
 int lbm_nn_bias_grad(const float* dY, int c, int64_t P, float* db, double* scratch, void* stream) {
     if (!dY || !db || !scratch || c < 1 || c > 65535 || P < 1) return LBM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_bias_partial, dim3(kBiasChunks, c), dim3(256), 0, st, dY, P, scratch);
+    hipLaunchKernelGGL(k_bias_final, dim3((c + 127) / 128), dim3(128), 0, st, scratch, c, db);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_bias_grad_noalloc(const float* dY, int c, int64_t P, float* db, void* stream) {
+    if (!dY || !db || c < 1 || c > kBiasNoallocMaxC || P < 1) return LBM_ERR_ARG;
+    double* scratch = nullptr;
+    const int rc = bias_scratch_ptr(&scratch);
+    if (rc != LBM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_bias_partial, dim3(kBiasChunks, c), dim3(256), 0, st, dY, P, scratch);
     hipLaunchKernelGGL(k_bias_final, dim3((c + 127) / 128), dim3(128), 0, st, scratch, c, db);

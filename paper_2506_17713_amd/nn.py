@@ -14,7 +14,8 @@ from . import lbm
 BF16, FP32 = 0, 1
 EXPORTS = ["lbm_nn_packed_words", "lbm_nn_pack", "lbm_nn_conv_work_bytes", "lbm_nn_conv", "lbm_nn_wgrad_partial_words", "lbm_nn_wgrad",
            "lbm_nn_bias_grad", "lbm_nn_relu_bwd", "lbm_nn_add", "lbm_nn_pool", "lbm_nn_pool_bwd", "lbm_nn_up",
-           "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam", "lbm_nn_augment", "lbm_nn_warm_fields"]
+           "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam", "lbm_nn_augment", "lbm_nn_warm_fields",
+           "lbm_nn_bias_grad_noalloc"]
 
 _lib = None
 
@@ -34,6 +35,7 @@ def load():
         lib.lbm_nn_wgrad_partial_words.restype = C.c_size_t
         lib.lbm_nn_wgrad.argtypes = [vp, i, vp, i, i, i, i, vp, vp, i, vp]
         lib.lbm_nn_bias_grad.argtypes = [vp, i, i64, vp, vp, vp]
+        lib.lbm_nn_bias_grad_noalloc.argtypes = [vp, i, i64, vp, vp]
         lib.lbm_nn_relu_bwd.argtypes = [vp, vp, i64, vp]
         lib.lbm_nn_add.argtypes = [vp, vp, i64, vp]
         lib.lbm_nn_pool.argtypes = [vp, i, i, i, i, vp, vp]
