@@ -92,6 +92,14 @@ typedef struct lbm_params {
     double body_accel[3];       /* body acceleration (x, y, z): F^k += rho^k a  */
     double wet[2];              /* uniform phi or drho when no per-node array   */
     double rho_min[2], rho_max[2]; /* virtual-density limiter bounds            */
+    double kappa[2];            /* surface-tension adjustment kappa^k (Sec. 2.3,
+                                   Eq. 14-16): D2Q9 MRT adds the moment source
+                                   C built from the pressure-tensor term Q, and
+                                   the surface tension falls about as 1 - kappa
+                                   with the coexistence densities unchanged.
+                                   Q takes the factor g_kk, which the printed
+                                   Eq. 16 leaves out.  0 = off; nonzero with
+                                   D3Q19 or BGK: LBM_ERR_UNSUPPORTED           */
 } lbm_params;
 
 typedef struct lbm_stats_t {
@@ -192,9 +200,9 @@ int lbm_set_state(lbm_handle* h, const void* dev_src);
  *   LBM_OBS_DRHO        L = sum_x dL_drho[x] rho(x) with a caller-given device
  *                       array dL_drho[N] of the compute type (any objective
  *                       linearised in the final density).
- * Supported for one component with LBM_STORE_F32 or LBM_STORE_F64; other
- * configurations (two components, 16-bit storage, LBM_STORE_F32_F64) return
- * LBM_ERR_UNSUPPORTED.
+ * Supported for one component with LBM_STORE_F32 or LBM_STORE_F64 and no
+ * surface-tension source; other configurations (two components, 16-bit
+ * storage, LBM_STORE_F32_F64, kappa != 0) return LBM_ERR_UNSUPPORTED.
  * ------------------------------------------------------------------------ */
 enum { LBM_OBS_SATURATION = 0, LBM_OBS_DRHO = 1 };
 

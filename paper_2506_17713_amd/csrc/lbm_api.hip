@@ -54,6 +54,9 @@ int validate(const lbm_params* p) {
         if (p->psi_kind[k] != LBM_PSI_CS && p->psi_kind[k] != LBM_PSI_DENSITY) return LBM_ERR_ARG;
         if (p->wet_mode[k] != LBM_WET_PHI && p->wet_mode[k] != LBM_WET_DRHO) return LBM_ERR_ARG;
         if (!(p->rho_min[k] <= p->rho_max[k])) return LBM_ERR_ARG;
+        if (!std::isfinite(p->kappa[k])) return LBM_ERR_ARG;
+        // the surface-tension source is defined for D2Q9 MRT (Eq. 15)
+        if (p->kappa[k] != 0.0 && (p->lattice != LBM_D2Q9 || p->collision != LBM_MRT)) return LBM_ERR_UNSUPPORTED;
         if (p->collision == LBM_MRT)
             for (int m = 0; m < q_of(p->lattice); ++m)
                 if (!(p->mrt_s[k][m] >= 0.0 && p->mrt_s[k][m] < 2.0)) return LBM_ERR_ARG;
@@ -157,6 +160,7 @@ void fill_args(lbm_handle* h, StepArgs<R>& a, const Buffers* bufs) {
         for (int kk = 0; kk < p.n_comp; ++kk) a.g[k][kk] = (R)p.g[k][kk];
         a.rho_min[k] = (R)p.rho_min[k];
         a.rho_max[k] = (R)p.rho_max[k];
+        a.kq[k] = (R)(p.kappa[k] * p.g[k][k]);
     }
     for (int d = 0; d < 3; ++d) a.body[d] = (R)p.body_accel[d];
 }

@@ -347,6 +347,7 @@ struct StepArgs {
     R g[2][2];
     R body[3];
     R rho_min[2], rho_max[2];
+    R kq[2];               // surface-tension source (D2Q9 MRT): kappa_k g_kk
 };
 
 __device__ __forceinline__ int wrap_near(int v, int n) {
@@ -1131,6 +1132,49 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
                         }
                         m[mm] = s;
                     });
+                    if constexpr (LAT == LAT_D2Q9) {
+                        // surface-tension source (Eq. 14-16): C in moment space,
+                        // C = [0, 1.5 s_e tr Q, -1.5 s_eps tr Q, 0, 0, 0, 0,
+                        //      -s_pxx (Q_xx - Q_yy), -s_pxy Q_xy], with
+                        // Q = kappa g [(1 - A) psi sum_i G_i (psi(x + e_i) - psi) e_i e_i
+                        //              + (A / 2) sum_i G_i (psi(x + e_i)^2 - psi^2) e_i e_i];
+                        // f* = f - M^-1 (S (m - m^eq) - C), and m here already holds
+                        // the relaxed moments divided by |row|^2
+                        if (P.kq[k] != (R)0) {
+                            const R ps = s_psi[sc][k][pc];
+                            R sxx = 0, syy = 0, sxy = 0, txx = 0, tyy = 0, txy = 0;
+                            sfor<Q - 1>([&](auto I) {
+                                constexpr int i = decltype(I)::value + 1;
+                                constexpr R Gi = (R)(3.0 * L::w(i));
+                                constexpr int ex = L::ex[i], ey = L::ey[i];
+                                const R pm = s_psi[(c + L::ec(i) - c0 + 3) % 3][k][pc + L::eb(i) * PWA + L::ea(i)];
+                                const R av = Gi * (pm - ps), bv = Gi * (pm * pm - ps * ps);
+                                if constexpr (ex != 0) {
+                                    sxx += av;
+                                    txx += bv;
+                                }
+                                if constexpr (ey != 0) {
+                                    syy += av;
+                                    tyy += bv;
+                                }
+                                if constexpr (ex * ey > 0) {
+                                    sxy += av;
+                                    txy += bv;
+                                } else if constexpr (ex * ey < 0) {
+                                    sxy -= av;
+                                    txy -= bv;
+                                }
+                            });
+                            const R c1 = P.kq[k] * ((R)1 - P.A[k]) * ps, c2 = P.kq[k] * (R)0.5 * P.A[k];
+                            const R Qxx = c1 * sxx + c2 * txx, Qyy = c1 * syy + c2 * tyy;
+                            const R Qxy = c1 * sxy + c2 * txy;
+                            const R tr = Qxx + Qyy;
+                            m[1] -= (R)1.5 * P.srate[k][1] * tr;
+                            m[2] += (R)1.5 * P.srate[k][2] * tr;
+                            m[7] += P.srate[k][7] * (Qxx - Qyy);
+                            m[8] += P.srate[k][8] * Qxy;
+                        }
+                    }
                     sfor<NP>([&](auto PI) {
                         constexpr int p = decltype(PI)::value;
                         constexpr int i = 2 * p + 1;

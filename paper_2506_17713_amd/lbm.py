@@ -41,7 +41,7 @@ class LbmParams(C.Structure):
         ("eos_a", C.c_double * 2), ("eos_b", C.c_double * 2), ("eos_R", C.c_double * 2),
         ("eos_T", C.c_double * 2), ("alpha", C.c_double * 2), ("A", C.c_double * 2),
         ("g", (C.c_double * 2) * 2), ("body_accel", C.c_double * 3), ("wet", C.c_double * 2),
-        ("rho_min", C.c_double * 2), ("rho_max", C.c_double * 2),
+        ("rho_min", C.c_double * 2), ("rho_max", C.c_double * 2), ("kappa", C.c_double * 2),
     ]
 
 
@@ -129,6 +129,7 @@ def params_from(w, check_every: int = 0) -> LbmParams:
             p.g[k][kk] = w.g[k][kk]
         p.wet[k] = w.wet[k]
         p.rho_min[k], p.rho_max[k] = w.rho_min[k], min(w.rho_max[k], 1e300)
+        p.kappa[k] = w.kappa[k]
     for d in range(3):
         p.body_accel[d] = w.body[d]
     return p

@@ -329,6 +329,68 @@ def test_mrt_nonunit_rates_d2q9_f64(oracle_mod):
     assert_tol(out, 1e-10)
 
 
+# ------------------------------------------------- surface-tension source (D2Q9)
+D2Q9_RATES_ST = (1.0, 1.1, 1.1, 1.0, 1.1, 1.0, 1.1, 1.0, 1.0)
+
+
+@pytest.mark.parametrize("storage,tol", [("F64", 1e-10), ("F32", 1e-4)])
+@pytest.mark.parametrize("kappa", [0.5, 0.99])
+def test_surface_tension_source_d2q9(oracle_mod, storage, tol, kappa):
+    """D2Q9 MRT with the surface-tension source (Sec. 2.3, Eq. 14-16): a drop
+    resting on a wall (solid neighbours enter Q through their virtual
+    density) in a ragged 70 x 45 domain, calibrated Zhang-Chen weight A."""
+    c = inputs.load_coexistence()["CS"]["0.8"]
+    shape = (1, 45, 70)
+    w = inputs.Workload("surface_tension_2d", "D2Q9", shape, collision="MRT", storage=storage, tau=(1.0, 1.0),
+                        mrt_s=(D2Q9_RATES_ST, D2Q9_RATES_ST), eos_T=(c["T"],) * 2, A=(c["A"],) * 2,
+                        wet_mode=("PHI", "PHI"), wet=(1.1, 1.1), rho_min=(c["rho_v"],) * 2,
+                        rho_max=(c["rho_l"],) * 2, kappa=(kappa, kappa))
+    solid = inputs.walls(shape, "y", (0,))
+    rho = inputs.droplet(shape, (35.0, 1.0, 0.0), 14, 3, c["rho_l"], c["rho_v"])[None]
+    out, _, _ = run_pair(oracle_mod, w, solid, rho, 500)
+    assert_tol(out, tol)
+
+
+def test_surface_tension_table2_on_gpu():
+    """Table 2 on the GPU at the paper's setting: D2Q9 MRT, CS at T_r = 0.8,
+    200^2 periodic, drops of radius 25-50 with interface width 3, tau = 1;
+    sigma from Laplace's law at 1 - kappa = 1, 0.5, 0.01.  A = 0 (the paper
+    does not print its A; the (1 - A) weight of Eq. 16 makes the ratios
+    depend on it).  The ratios must follow Table 2's 0.457 and 0.0091."""
+    import math
+
+    from oracle import eos
+    from paper_2506_17713_amd import lbm
+
+    c = inputs.load_coexistence()["CS"]["0.8"]
+    n = 200
+    sig = {}
+    for kappa in (0.0, 0.5, 0.99):
+        dps, req = [], []
+        for R in (25, 30, 35, 40, 45, 50):
+            w = inputs.Workload("table2", "D2Q9", (1, n, n), collision="MRT", storage="F64", tau=(1.0, 1.0),
+                                mrt_s=(D2Q9_RATES_ST, D2Q9_RATES_ST), eos_T=(c["T"],) * 2,
+                                rho_min=(c["rho_v"],) * 2, rho_max=(c["rho_l"],) * 2, kappa=(kappa, kappa))
+            rho = inputs.droplet((1, n, n), (n / 2, n / 2, 0.0), R, 3.0, c["rho_l"], c["rho_v"])[None]
+            sol = lbm.Solver(w, np.zeros((1, n, n), np.uint8), rho)
+            sol.step(20000)
+            r, _ = sol.moments_numpy(-1)
+            sol.close()
+            r = r.reshape(n, n)
+            rin, rout = r[n // 2, n // 2], r[0, 0]
+            dps.append(eos.CS.pressure(rin, c["T"]) - eos.CS.pressure(rout, c["T"]))
+            req.append(math.sqrt(((r - rout) / (rin - rout)).sum() / math.pi))
+        x, y = 1.0 / np.array(req), np.array(dps)
+        (s, icpt), res, *_ = np.linalg.lstsq(np.vstack([x, np.ones_like(x)]).T, y, rcond=None)
+        sig[kappa] = float(s)
+        print(f"1 - kappa = {1 - kappa:.2f}: sigma {s:.6f} intercept {icpt:.2e}", flush=True)
+    rec = {"case": "surface_tension_table2", "sigma": {str(k): v for k, v in sig.items()},
+           "ratio_0.5": sig[0.5] / sig[0.0], "ratio_0.01": sig[0.99] / sig[0.0]}
+    _report(rec)
+    assert abs(sig[0.5] / sig[0.0] - 0.457) < 0.03
+    assert abs(sig[0.99] / sig[0.0] - 0.0091) < 0.05
+
+
 # ------------------------------------------------------- 16-bit deviation storage
 @pytest.mark.parametrize("storage", ["F16DEV", "BF16DEV"])
 def test_deviation_storage_error_is_reported(oracle_mod, storage):
