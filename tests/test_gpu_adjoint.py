@@ -154,6 +154,36 @@ def test_adjoint_f32_matches_oracle_on_pack_crop(oracle_mod):
     assert rel < 1e-3 and relT < 1e-3
 
 
+def test_adjoint_f32_crop32_1000_steps_vs_oracle_golden():
+    """The adjoint workload's oracle check as stated: the 32^3 crop of the
+    128^3 pack (x, y, z in [0, 32), periodic), 1,000 FP32 steps with a
+    checkpoint every 100, against the FP64 oracle's complex-step derivatives
+    at 20 boundary voxels and T, stored by tests/golden/make_c4_crop32.py."""
+    import hashlib
+    import importlib.util
+    from pathlib import Path
+
+    gdir = Path(__file__).resolve().parent / "golden"
+    spec = importlib.util.spec_from_file_location("make_c4_crop32", gdir / "make_c4_crop32.py")
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    gold = json.loads((gdir / "c4_crop32_cstep.json").read_text())
+    w, solid, rho = mk.crop_workload()
+    assert hashlib.sha256(solid.tobytes()).hexdigest() == gold["solid_sha256"]
+    w = w.with_(storage="F32")
+    print("case adjoint F32 crop32, 1000 steps, checkpoint 100", flush=True)
+    L, g, dT = gpu_grad(w, solid, rho, gold["steps"], 100)
+    vox = np.array(gold["voxels"])
+    go = np.array(gold["dS_dphi"])
+    rel = np.abs(g[vox] - go).max() / np.abs(go).max()
+    relT = abs(dT - gold["dS_dT"]) / abs(gold["dS_dT"])
+    _report({"case": "adjoint_f32_crop32_1000", "L": L, "L_oracle": gold["S"], "rel_err_dphi": rel,
+             "rel_err_dT": relT})
+    print(L, gold["S"], rel, relT, flush=True)
+    assert abs(L - gold["S"]) < 1e-5
+    assert rel < 1e-3 and relT < 1e-3
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     w, solid, rho = small_sessile("F32")
     a = gpu_grad(w, solid, rho, 50, 50)

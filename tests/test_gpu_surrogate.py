@@ -27,7 +27,8 @@ def ops():
     return nn
 
 
-SHAPES = [(1, 16, (8, 6, 10)), (16, 3, (8, 8, 8)), (35, 40, (6, 10, 12)), (64, 64, (4, 4, 4))]
+SHAPES = [(1, 16, (8, 6, 10)), (16, 3, (8, 8, 8)), (35, 40, (6, 10, 12)), (64, 64, (4, 4, 4)),
+          (128, 128, (4, 6, 8)), (64, 128, (6, 6, 6))]
 
 
 @pytest.mark.parametrize("cin,cout,dhw", SHAPES)
@@ -63,7 +64,11 @@ def test_conv_data_gradient(T, ops, cin, cout, dhw, prec, tol):
     assert rel(dX, nn_ref.dgrad(W, dY)) < tol
 
 
-@pytest.mark.parametrize("cin,cout,dhw", SHAPES + [(16, 32, (32, 32, 32))])
+# (16, 32, 32^3) and (8, 16, 40 x 40 x 48) take the 8- and 64-chunk paths of the
+# weight gradient (P >= 4,096 and P >= 65,536), the latter the one every
+# 64^3 and 128^3 training layer takes; (32, 128, 16^3) a 128-channel layer
+@pytest.mark.parametrize("cin,cout,dhw", SHAPES + [(16, 32, (32, 32, 32)), (8, 16, (40, 40, 48)),
+                                                  (32, 128, (16, 16, 16))])
 @pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 2e-2)])
 def test_conv_weight_gradient(T, ops, cin, cout, dhw, prec, tol):
     from oracle import nn_ref
