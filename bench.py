@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="after the run, two plain device copies of this many GiB (hardware-counter calibration)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="no GPU work: read the rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output of two runs of "
+                         "'bench.py --copy-gib 1' and write profiles/k_step_traffic.json for the kernel sources "
+                         "in this tree")
     return ap.parse_args()
 
 
@@ -67,22 +71,77 @@ def algorithmic_bytes(w, solid) -> float:
     return float(n_fluid * per_fluid + w.N)
 
 
+KERNEL_SOURCES = ("paper_2506_17713_amd/csrc/lbm_device.hpp", "paper_2506_17713_amd/csrc/lbm_api.hip",
+                  "paper_2506_17713_amd/csrc/lbm_internal.hpp")
+HEADLINE_KERNEL = "k_step<1, 1, 1, 1, false"  # D3Q19, one component, FP32, MRT, step
+
+
+def sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update((ROOT / p).read_bytes())
+    return h.hexdigest()
+
+
+def record_traffic(fetch_dir: str, write_dir: str) -> dict:
+    """Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of the headline kernel from
+    two rocprofv3 --pmc runs of 'bench.py --copy-gib 1', each scaled by the
+    same counter on the run's two plain 1 GiB copies (which read and write
+    exactly 1 GiB each); written with the hash of the kernel sources of this
+    tree, which bench.py compares before reporting roofline.traffic."""
+    import csv
+    import statistics
+
+    def rows(d, counter):
+        out = []
+        for f in sorted(Path(d).rglob("*counter_collection.csv")):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r.get("Counter_Name") == counter:
+                        out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return out
+
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rs = rows(d, counter)
+        k = [v for n, v in rs if HEADLINE_KERNEL in n]
+        cp = [v for n, v in rs if "copyBuffer" in n]
+        if not k or len(cp) < 2:
+            raise SystemExit(f"{counter}: kernel or copy dispatches not found under {d}")
+        res[counter] = (statistics.mean(k), cp[-2:])
+    copy_bytes = 1 << 30
+    rf = copy_bytes / (1024.0 * statistics.mean(res["FETCH_SIZE"][1]))
+    wf = copy_bytes / (1024.0 * statistics.mean(res["WRITE_SIZE"][1]))
+    rec = {
+        "kernel": HEADLINE_KERNEL + ", ...> (sessile droplet D3Q19 MRT FP32 256^3, bench.py default)",
+        "kernel_source_sha256": sources_sha256(),
+        "fetch_kib_per_dispatch": res["FETCH_SIZE"][0], "write_kib_per_dispatch": res["WRITE_SIZE"][0],
+        "copy_fetch_kib": res["FETCH_SIZE"][1], "copy_write_kib": res["WRITE_SIZE"][1], "copy_bytes": copy_bytes,
+        "read_factor": rf, "write_factor": wf,
+        "traffic_bytes_per_launch": res["FETCH_SIZE"][0] * 1024 * rf + res["WRITE_SIZE"][0] * 1024 * wf,
+        "command_fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d " + fetch_dir +
+                         " -o run -- python3 -u bench.py --steps 5 --warmup 1 --no-cpu-baseline --copy-gib 1",
+        "command_write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d " + write_dir +
+                         " -o run -- python3 -u bench.py --steps 5 --warmup 1 --no-cpu-baseline --copy-gib 1",
+        "command_record": f"python bench.py --record-traffic {fetch_dir} {write_dir}",
+    }
+    (ROOT / "profiles" / "k_step_traffic.json").write_text(json.dumps(rec, indent=1) + "\n")
+    return rec
+
+
 def measured_traffic(w, name: str) -> float | None:
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
     measurement (profiles/k_step_traffic.json), scaled by the same counters on
     a 1 GiB copy; None if the kernel sources changed since, or for another
     workload."""
-    import hashlib
-
     path = ROOT / "profiles" / "k_step_traffic.json"
     if (not path.exists() or name != "sessile" or w.storage != "F32" or w.collision != "MRT"
             or w.shape != (256, 256, 256)):
         return None
     rec = json.loads(path.read_text())
-    h = hashlib.sha256()
-    for p in ("paper_2506_17713_amd/csrc/lbm_device.hpp", "paper_2506_17713_amd/csrc/lbm_api.hip"):
-        h.update((ROOT / p).read_bytes())
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["kernel_source_sha256"] else None
+    return rec["traffic_bytes_per_launch"] if sources_sha256() == rec["kernel_source_sha256"] else None
 
 
 def make_workload(name: str, n: int, storage: str, collision: str):
@@ -250,6 +309,9 @@ def run_surrogate(args) -> dict:
 
 def main():
     args = parse()
+    if args.record_traffic:
+        print(json.dumps(record_traffic(*args.record_traffic), indent=1))
+        return
     if args.steps is None:
         args.steps = {"adjoint": 1000, "surrogate": 20}.get(args.workload, 500)
     if args.gpus != 1:

@@ -50,6 +50,7 @@ struct lbm_handle {
     int64_t since_check;
     bool have_prev;
     bool wet_uniform;  // no per-node wetting field was given: p.wet[k] everywhere
+    bool mostly_fluid; // under 10 % solid nodes: tiles carry even work
     int chunk_override;
 };
 
