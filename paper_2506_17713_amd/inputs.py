@@ -208,12 +208,14 @@ def droplet_2d(n=128, steps=2000, storage="F64", r=20.0, w=5.0, tr=0.7, seed=0, 
 
 
 def sessile_3d(n=256, steps=20000, storage="F32", r=30.0, w=5.0, tr=0.8, wet_mode="PHI",
-               wet=1.0, collision="MRT", nxy=None, center=None):
+               wet=1.0, collision="MRT", nxy=None, center=None, vapour=None):
     """D3Q19 Carnahan-Starling droplet resting on a solid wall at z = 0 (and a
     second wall at z = nz-1); x and y periodic.  MRT takes the d'Humieres
     rates at tau = 1 (with tau = 1 and every other rate 1 it would reduce to
-    BGK)."""
+    BGK).  The vapour starts at the Maxwell density unless `vapour` is given
+    (the limiter bounds stay at the Maxwell pair)."""
     T, rv, rl, A = _cs(tr)
+    rv_init = rv if vapour is None else vapour
     nx = ny = nxy or n
     shape = (n, ny, nx)
     dh = dhumieres_rates(1.0)
@@ -222,7 +224,7 @@ def sessile_3d(n=256, steps=20000, storage="F32", r=30.0, w=5.0, tr=0.8, wet_mod
                   wet=(wet, wet), rho_min=(rv, rv), rho_max=(rl, rl), steps=steps)
     solid = walls(shape, "z", (0, n - 1))
     c = center or (nx / 2, ny / 2, r + 1.0)
-    rho = droplet(shape, c, r, w, rl, rv)
+    rho = droplet(shape, c, r, w, rl, rv_init)
     return wl, solid, rho[None]
 
 

@@ -624,3 +624,20 @@ def test_nonfinite_state_is_detected():
     assert sol.sync() == -4
     s = sol.stats()
     assert s["rc"] == -4 and s["nonfinite"] > 0
+
+
+# ------------------------------------------------------------- wetting (Eq. 17)
+def test_contact_angle_follows_the_wetting_parameter():
+    """Sessile drops on the GPU (D3Q19 MRT, 96^3, r = 15, 4,000 steps): the
+    measured contact angle falls with phi, rises with drho, and phi = 1 lies
+    between the two families."""
+    from paper_2506_17713_amd import wetting
+
+    th = {}
+    for mode, val in (("PHI", 1.3), ("PHI", 1.0), ("DRHO", 0.02)):
+        th[(mode, val)] = wetting.run(mode, val, n=96, r=15.0, steps=4000)[0]
+    print(th, flush=True)
+    _report({"case": "contact_angle_96", "angles": {f"{m}{v}": a for (m, v), a in th.items()}})
+    assert th[("PHI", 1.3)] < th[("PHI", 1.0)] - 15
+    assert th[("DRHO", 0.02)] > th[("PHI", 1.0)] + 10
+    assert 70 < th[("PHI", 1.0)] < 100
