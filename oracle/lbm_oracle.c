@@ -16,7 +16,9 @@
  *   4. Shan-Chen / Zhang-Chen interaction force + body force     (Eq. 13)
  *   5. equilibrium velocity (bare j/rho; common velocity for two components)
  *   6. BGK or MRT collision, then exact-difference forcing      (Eq. 3, Eq. 5);
- *      D2Q9 MRT optionally with the surface-tension source C    (Eq. 14-16)
+ *      D2Q9 MRT optionally with the surface-tension source C    (Eq. 14-16);
+ *      or the central-moment (cascaded) collision with the
+ *      consistent forcing term of the same moments               (Eq. 3, Eq. 7-8)
  *   7. streaming with halfway bounce-back at solid nodes        (Eq. 2)
  * Macroscopic velocity output uses the half-force correction   (Eq. 6).
  *
@@ -56,7 +58,7 @@ typedef struct {
     int lattice;          /* 0 = D2Q9, 1 = D3Q19                              */
     int nx, ny, nz;       /* domain; nz = 1 for D2Q9                         */
     int nc;               /* number of fluid components (1 or 2)             */
-    int collision;        /* 0 = BGK, 1 = MRT                                */
+    int collision;        /* 0 = BGK, 1 = MRT, 2 = central moments (CLBM)   */
     int psi_kind[MAXC];   /* 0 = Carnahan-Starling EOS, 1 = psi = rho        */
     int wet_mode[MAXC];   /* 0 = phi * rho_ave, 1 = rho_ave - drho           */
     int common_velocity;  /* two components: 1 = common velocity u'         */
@@ -169,6 +171,32 @@ static void build_mrt(const lattice_t *L, double M[MAXQ][MAXQ])
         }
     }
 }
+
+#ifndef ORACLE_CSTEP
+/* Central-moment transform: the rows of build_mrt evaluated at the peculiar
+ * velocities e_i - u instead of e_i (CLBM, Eq. 3: N M with N the shift from
+ * raw to central moments, so that N M = T(u) with rows P_a(e_i - u)). */
+static void build_central(const lattice_t *L, const double u[3], double T[MAXQ][MAXQ])
+{
+    memset(T, 0, sizeof(double) * MAXQ * MAXQ);
+    for (int i = 0; i < L->q; ++i) {
+        double ex = L->e[i][0] - u[0], ey = L->e[i][1] - u[1], ez = L->e[i][2] - u[2];
+        double e2 = ex * ex + ey * ey + ez * ez;
+        if (L->q == 9) {
+            double r[9] = {1.0, -4.0 + 3.0 * e2, 4.0 - 10.5 * e2 + 4.5 * e2 * e2, ex, (3.0 * e2 - 5.0) * ex,
+                           ey, (3.0 * e2 - 5.0) * ey, ex * ex - ey * ey, ex * ey};
+            for (int m = 0; m < 9; ++m) T[m][i] = r[m];
+        } else {
+            double r[19] = {1.0, 19.0 * e2 - 30.0, (21.0 * e2 * e2 - 53.0 * e2 + 24.0) / 2.0, ex,
+                            (5.0 * e2 - 9.0) * ex, ey, (5.0 * e2 - 9.0) * ey, ez, (5.0 * e2 - 9.0) * ez,
+                            3.0 * ex * ex - e2, (3.0 * e2 - 5.0) * (3.0 * ex * ex - e2), ey * ey - ez * ez,
+                            (3.0 * e2 - 5.0) * (ey * ey - ez * ez), ex * ey, ey * ez, ex * ez,
+                            (ey * ey - ez * ez) * ex, (ez * ez - ex * ex) * ey, (ex * ex - ey * ey) * ez};
+            for (int m = 0; m < 19; ++m) T[m][i] = r[m];
+        }
+    }
+}
+#endif
 
 /* General inverse by Gauss-Jordan elimination with partial pivoting. */
 static int invert(int n, double A[MAXQ][MAXQ], double Ainv[MAXQ][MAXQ])
@@ -448,6 +476,42 @@ static void fields(const oref_params *p, const geom_t *G, const uint8_t *solid,
 /* ------------------------------------------------------------------------ */
 /* Steps 5-7: equilibrium velocity, collision + EDM, streaming.             */
 /* ------------------------------------------------------------------------ */
+#ifndef ORACLE_CSTEP
+/* Central-moment collision with the consistent forcing of the same moments
+ * (Eq. 3 CLBM form, Eq. 7): with T = N M the central-moment transform at the
+ * velocity u = (j + F/2)/rho (Eq. 8),
+ *   f* = f + T^-1 [ -S T (f - f^eq) + (I - S/2) T R ],
+ *   R_i = (F / rho) . (e_i - u) / c_s^2  f^eq_i,
+ * and no exact-difference term. */
+static void collide_clbm(const lattice_t *L, const double *rates, double rho, const double u[3],
+                         const double F[3], const double *fi, double *fo)
+{
+    const int q = L->q;
+    double T[MAXQ][MAXQ], Ti[MAXQ][MAXQ], fe[MAXQ], R[MAXQ], y[MAXQ];
+    build_central(L, u, T);
+    invert(q, T, Ti);
+    feq(L, rho, u, fe);
+    for (int i = 0; i < q; ++i) {
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) s += F[d] * (L->e[i][d] - u[d]);
+        R[i] = 3.0 * s / rho * fe[i];
+    }
+    for (int a = 0; a < q; ++a) {
+        double z = 0.0, w = 0.0;
+        for (int i = 0; i < q; ++i) {
+            z += T[a][i] * (fi[i] - fe[i]);
+            w += T[a][i] * R[i];
+        }
+        y[a] = -rates[a] * z + (1.0 - 0.5 * rates[a]) * w;
+    }
+    for (int i = 0; i < q; ++i) {
+        double x = 0.0;
+        for (int a = 0; a < q; ++a) x += Ti[i][a] * y[a];
+        fo[i] = fi[i] + x;
+    }
+}
+#endif
+
 static void collide(const oref_params *p, const geom_t *G, const uint8_t *solid,
                     const real_t *f, const work_t *W, double M[MAXQ][MAXQ],
                     double Minv[MAXQ][MAXQ], real_t *fpost)
@@ -475,6 +539,20 @@ static void collide(const oref_params *p, const geom_t *G, const uint8_t *solid,
         }
         for (int k = 0; k < nc; ++k) {
             real_t rho = W->rho[(long)k * N + n];
+#ifndef ORACLE_CSTEP
+            if (p->collision == 2) {
+                /* one component: u = (j + F/2)/rho (Eq. 8) */
+                double uc[3], Fk[3], fi[MAXQ], fo[MAXQ];
+                for (int d = 0; d < 3; ++d) {
+                    Fk[d] = W->F[((long)k * 3 + d) * N + n];
+                    uc[d] = (W->j[((long)k * 3 + d) * N + n] + 0.5 * Fk[d]) / rho;
+                }
+                for (int i = 0; i < q; ++i) fi[i] = f[((long)k * q + i) * N + n];
+                collide_clbm(L, p->mrt_s[k], rho, uc, Fk, fi, fo);
+                for (int i = 0; i < q; ++i) fpost[((long)k * q + i) * N + n] = fo[i];
+                continue;
+            }
+#endif
             real_t u[3];
             for (int d = 0; d < 3; ++d)
                 u[d] = (nc > 1 && p->common_velocity) ? ucom[d]
@@ -602,6 +680,10 @@ void oref_collide_node(const oref_params *p, int k, const double *fin, const dou
     invert(L.q, M, Mi);
     double rho = 0.0;
     for (int i = 0; i < L.q; ++i) rho += fin[i];
+    if (p->collision == 2) {
+        collide_clbm(&L, p->mrt_s[k], rho, u, F, fin, fout);
+        return;
+    }
     double fe[MAXQ], fe2[MAXQ], u2[3];
     feq(&L, rho, u, fe);
     if (p->collision == 0) {
@@ -656,6 +738,10 @@ int API(step)(const oref_params *p, const uint8_t *solid, const real_t *wet, rea
     if (p->nc < 1 || p->nc > MAXC) return -1;
     for (int k = 0; k < p->nc; ++k)
         if (p->kappa[k] != 0.0 && (p->lattice != 0 || p->collision != 1)) return -4;
+    if (p->collision == 2 && p->nc != 1) return -4;
+#ifdef ORACLE_CSTEP
+    if (p->collision == 2) return -4;
+#endif
     if (geom_init(p, &G)) return -2;
     build_mrt(&G.L, M);
     if (invert(G.L.q, M, Mi)) return -3;

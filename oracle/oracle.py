@@ -79,7 +79,7 @@ def params_from(w, T_im: float | tuple = 0.0) -> OrefParams:
     nx, ny, nz = w.shape_xyz
     p.nx, p.ny, p.nz = nx, ny, nz
     p.nc = w.nc
-    p.collision = 0 if w.collision == "BGK" else 1
+    p.collision = {"BGK": 0, "MRT": 1, "CLBM": 2}[w.collision]
     p.common_velocity = 1 if w.common_velocity else 0
     tim = T_im if isinstance(T_im, (tuple, list)) else (T_im, T_im)
     for k in range(w.nc):

@@ -46,7 +46,7 @@ class Workload:
     lattice: str                      # "D2Q9" or "D3Q19"
     shape: tuple                      # (nz, ny, nx)
     nc: int = 1
-    collision: str = "BGK"            # "BGK" or "MRT"
+    collision: str = "BGK"            # "BGK", "MRT" or "CLBM" (central moments)
     storage: str = "F32"              # "F64", "F32", "F32F64", "F16DEV", "BF16DEV"
     tau: tuple = (1.0, 1.0)
     mrt_s: tuple | None = None        # explicit rates per component, else defaults
