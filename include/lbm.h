@@ -46,7 +46,11 @@ typedef enum lbm_error {
 } lbm_error;
 
 enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
-enum { LBM_BGK = 0, LBM_MRT = 1 };
+/* Collision (Eq. 3): BGK or MRT with exact-difference forcing (Eq. 5), or
+ * central moments (cascaded) with the consistent forcing of the same moments
+ * (Eq. 7-8; D2Q9, one component; rates in mrt_s on the MRT rows evaluated at
+ * the peculiar velocities e_i - u). */
+enum { LBM_BGK = 0, LBM_MRT = 1, LBM_CLBM = 2 };
 /* Population storage.  F64 / F32 store f_i and compute in the same type.
  * F32_F64 stores f_i in FP32 and computes in FP64: the memory and HBM
  * traffic of FP32 with the accuracy that FP32 rounding of the stored state
@@ -68,7 +72,7 @@ typedef struct lbm_params {
     int32_t nx, ny, nz;         /* lattice extent; nz = 1 for D2Q9; at most
                                    2^31 - 1 nodes and nx*ny < 2^29 (3-D)       */
     int32_t n_comp;             /* 1 or 2 fluid components                     */
-    int32_t collision;          /* LBM_BGK or LBM_MRT                          */
+    int32_t collision;          /* LBM_BGK, LBM_MRT or LBM_CLBM                */
     int32_t storage;            /* LBM_STORE_*                                 */
     int32_t psi_kind[2];        /* LBM_PSI_* per component                     */
     int32_t wet_mode[2];        /* LBM_WET_* per component                     */
@@ -200,9 +204,10 @@ int lbm_set_state(lbm_handle* h, const void* dev_src);
  *   LBM_OBS_DRHO        L = sum_x dL_drho[x] rho(x) with a caller-given device
  *                       array dL_drho[N] of the compute type (any objective
  *                       linearised in the final density).
- * Supported for one component with LBM_STORE_F32 or LBM_STORE_F64 and no
- * surface-tension source; other configurations (two components, 16-bit
- * storage, LBM_STORE_F32_F64, kappa != 0) return LBM_ERR_UNSUPPORTED.
+ * Supported for one component with LBM_STORE_F32 or LBM_STORE_F64, BGK or
+ * MRT, and no surface-tension source; other configurations (two components,
+ * 16-bit storage, LBM_STORE_F32_F64, kappa != 0, LBM_CLBM) return
+ * LBM_ERR_UNSUPPORTED.
  * ------------------------------------------------------------------------ */
 enum { LBM_OBS_SATURATION = 0, LBM_OBS_DRHO = 1 };
 

@@ -44,7 +44,9 @@ int validate(const lbm_params* p) {
     // in-plane byte offsets are 32-bit (8-byte values at most)
     if ((long long)p->nx * (p->lattice == LBM_D2Q9 ? 1 : p->ny) >= (1LL << 29)) return LBM_ERR_ARG;
     if (p->n_comp < 1 || p->n_comp > 2) return LBM_ERR_ARG;
-    if (p->collision != LBM_BGK && p->collision != LBM_MRT) return LBM_ERR_ARG;
+    if (p->collision != LBM_BGK && p->collision != LBM_MRT && p->collision != LBM_CLBM) return LBM_ERR_ARG;
+    // central moments: one D2Q9 component (Eq. 3, Eq. 7-8)
+    if (p->collision == LBM_CLBM && (p->lattice != LBM_D2Q9 || p->n_comp != 1)) return LBM_ERR_UNSUPPORTED;
     if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F32_F64) return LBM_ERR_ARG;
     if (p->check_every < 0) return LBM_ERR_ARG;
     for (int i = 0; i < 4; ++i)
@@ -57,7 +59,7 @@ int validate(const lbm_params* p) {
         if (!std::isfinite(p->kappa[k])) return LBM_ERR_ARG;
         // the surface-tension source is defined for D2Q9 MRT (Eq. 15)
         if (p->kappa[k] != 0.0 && (p->lattice != LBM_D2Q9 || p->collision != LBM_MRT)) return LBM_ERR_UNSUPPORTED;
-        if (p->collision == LBM_MRT)
+        if (p->collision != LBM_BGK)
             for (int m = 0; m < q_of(p->lattice); ++m)
                 if (!(p->mrt_s[k][m] >= 0.0 && p->mrt_s[k][m] < 2.0)) return LBM_ERR_ARG;
         if (p->psi_kind[k] == LBM_PSI_CS) {
@@ -239,6 +241,8 @@ template <int LAT, int NC, int ST>
 hipError_t dispatch_coll(lbm_handle* h, bool mom, StepArgs<typename Store<ST>::R>& a) {
     if (mom) return launch_step<LAT, NC, ST, COLL_BGK, true>(h, a);
     if (h->p.collision == LBM_MRT) return launch_step<LAT, NC, ST, COLL_MRT, false>(h, a);
+    if constexpr (LAT == LAT_D2Q9 && NC == 1)
+        if (h->p.collision == LBM_CLBM) return launch_step<LAT, NC, ST, COLL_CLBM, false>(h, a);
     return launch_step<LAT, NC, ST, COLL_BGK, false>(h, a);
 }
 

@@ -29,7 +29,7 @@
 namespace lbm {
 
 enum { LAT_D2Q9 = 0, LAT_D3Q19 = 1 };
-enum { COLL_BGK = 0, COLL_MRT = 1 };
+enum { COLL_BGK = 0, COLL_MRT = 1, COLL_CLBM = 2 };
 enum { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32D = 4 };
 
 // ---------------------------------------------------------------------------
@@ -1077,6 +1077,110 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
                         const R so = (R)3 * (om * eu + ed);
                         fo[i] = om1 * f[k][i] + (wo + wr * (se + so));
                         fo[i + 1] = om1 * f[k][i + 1] + (wo + wr * (se - so));
+                    });
+                } else if constexpr (COLL == COLL_CLBM) {
+                    // Central moments with the consistent forcing (Eq. 3, Eq. 7-8),
+                    // one D2Q9 component:
+                    //   f* = f + T^-1 [-S T (f - f^eq) + (I - S/2) T R],
+                    //   R_i = (F / rho) . (e_i - u) / c_s^2 f^eq_i,  u = (j + F/2) / rho,
+                    // T = rows of the moment basis at e_i - u.  With m = M (f - f^eq)
+                    // and r = M R the raw moments, T = N M and N = T M^-1 = T M^T
+                    // diag(1 / |row|^2) has unit pivots for any |u| < 0.3, so
+                    // N v = y is solved without pivoting and f* = f + M^-1 v.
+                    static_assert(LAT == LAT_D2Q9, "central moments: D2Q9 only");
+                    const R uxc = (j[k][0] + (R)0.5 * F[k][0]) * invr;
+                    const R uyc = (j[k][1] + (R)0.5 * F[k][1]) * invr;
+                    const R us = (R)1.5 * (uxc * uxc + uyc * uyc);
+                    const R uF = uxc * F[k][0] + uyc * F[k][1];
+                    R d[Q], Rf[Q];
+                    sfor<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        const R wri = i == 0 ? wr0 : (L::w(i) == L::w(1) ? wrA : wrB);
+                        const R eu = dot_e<L::ex[i], L::ey[i], 0>(uxc, uyc, (R)0);
+                        const R fe = wri + wri * ((R)3 * eu + (R)4.5 * (eu * eu) - us);
+                        d[i] = f[k][i] - fe;
+                        Rf[i] = (R)3 * (dot_e<L::ex[i], L::ey[i], 0>(F[k][0], F[k][1], (R)0) - uF) * invr * fe;
+                    });
+                    // raw moments and the rows of N
+                    R m[Q], rr[Q], Nm[Q][Q];
+                    sfor<Q>([&](auto A) {
+                        constexpr int a = decltype(A)::value;
+                        R sm = 0, sr = 0;
+                        sfor<Q>([&](auto I) {
+                            constexpr int i = decltype(I)::value;
+                            constexpr double cf = mrt_coef<LAT>(a, i);
+                            if constexpr (cf != 0.0) {
+                                sm += (R)cf * d[i];
+                                sr += (R)cf * Rf[i];
+                            }
+                        });
+                        m[a] = sm;
+                        rr[a] = sr;
+                        sfor<Q>([&](auto B) { Nm[a][decltype(B)::value] = (R)0; });
+                    });
+                    sfor<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        const R cx = (R)L::ex[i] - uxc, cy = (R)L::ey[i] - uyc;
+                        const R c2 = cx * cx + cy * cy;
+                        const R row[9] = {(R)1,
+                                          (R)-4 + (R)3 * c2,
+                                          (R)4 - (R)10.5 * c2 + (R)4.5 * c2 * c2,
+                                          cx,
+                                          ((R)3 * c2 - (R)5) * cx,
+                                          cy,
+                                          ((R)3 * c2 - (R)5) * cy,
+                                          cx * cx - cy * cy,
+                                          cx * cy};
+                        sfor<Q>([&](auto B) {
+                            constexpr int b = decltype(B)::value;
+                            constexpr double cf = mrt_coef<LAT>(b, i) / mrt_norm<LAT>(b);
+                            if constexpr (cf != 0.0) {
+#pragma unroll
+                                for (int a = 0; a < Q; ++a) Nm[a][b] += row[a] * (R)cf;
+                            }
+                        });
+                    });
+                    // y = -S N m + (I - S/2) N r, then N v = y by elimination
+                    R y[Q];
+                    sfor<Q>([&](auto A) {
+                        constexpr int a = decltype(A)::value;
+                        R z = 0, w2 = 0;
+#pragma unroll
+                        for (int b = 0; b < Q; ++b) {
+                            z += Nm[a][b] * m[b];
+                            w2 += Nm[a][b] * rr[b];
+                        }
+                        const R sa = P.srate[k][a] * (R)mrt_norm<LAT>(a);
+                        y[a] = -sa * z + ((R)1 - (R)0.5 * sa) * w2;
+                    });
+#pragma unroll
+                    for (int c = 0; c < Q; ++c) {
+                        const R ip = (R)1 / Nm[c][c];
+#pragma unroll
+                        for (int r = c + 1; r < Q; ++r) {
+                            const R l = Nm[r][c] * ip;
+#pragma unroll
+                            for (int b = c + 1; b < Q; ++b) Nm[r][b] -= l * Nm[c][b];
+                            y[r] -= l * y[c];
+                        }
+                    }
+                    R v[Q];
+#pragma unroll
+                    for (int c = Q - 1; c >= 0; --c) {
+                        R t = y[c];
+#pragma unroll
+                        for (int b = c + 1; b < Q; ++b) t -= Nm[c][b] * v[b];
+                        v[c] = t / Nm[c][c];
+                    }
+                    sfor<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        R x = 0;
+                        sfor<Q>([&](auto B) {
+                            constexpr int b = decltype(B)::value;
+                            constexpr double cf = mrt_coef<LAT>(b, i) / mrt_norm<LAT>(b);
+                            if constexpr (cf != 0.0) x += (R)cf * v[b];
+                        });
+                        fo[i] = f[k][i] + x;
                     });
                 } else {
                     // f* = f - M^-1 S M (f - f^eq) + dF with M^-1 = M^T diag(1/|row|^2)

@@ -111,7 +111,7 @@ def params_from(w, check_every: int = 0) -> LbmParams:
     p.lattice = 0 if w.lattice == "D2Q9" else 1
     p.nx, p.ny, p.nz = w.shape_xyz
     p.n_comp = w.nc
-    p.collision = 0 if w.collision == "BGK" else 1
+    p.collision = {"BGK": 0, "MRT": 1, "CLBM": 2}[w.collision]
     p.storage = STORAGE[w.storage]
     p.common_velocity = 1 if w.common_velocity else 0
     p.check_every = check_every

@@ -197,7 +197,8 @@ def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, rho0=None, tol=1e-6, ch
     changed by less than k_tol (relative) over two consecutive checks: the
     time-to-permeability stopping rule, which needs no converged answer.
     Returns dict(u [3, N] and rho [N] torch tensors, steps, seconds, k,
-    residual, k_steps, k_seconds, k_at_k_steps, history)."""
+    residual, k_steps, k_seconds, k_at_k_steps, history of (steps, residual,
+    k, seconds) per check)."""
     w, solid, rho = inputs.single_phase_pack(shape=solid.shape, solid=solid, accel=accel, storage=storage)
     on_device = isinstance(rho0, torch.Tensor)
     if rho0 is not None and not on_device:
@@ -218,7 +219,7 @@ def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, rho0=None, tol=1e-6, ch
         res = st["residual"]
         k = NU * st["mean_ux"] * porosity / accel
         now = time.perf_counter() - t0
-        hist.append((steps, res, k))
+        hist.append((steps, res, k, now))
         if k_prev is not None and abs(k - k_prev) < k_tol * abs(k):
             calm += 1
             if calm == 2 and k_hit is None:
@@ -360,3 +361,13 @@ def train(model: Surrogate, xs, ys, epochs: int, lr=1e-3, log=print, seed=0, aug
         hist.append(tot / len(xs))
         log(f"epoch {ep}: mse {hist[-1]:.5f}")
     return hist
+
+
+def first_within(history, k_ref: float, tol: float = 0.01):
+    """(steps, seconds) of the first check whose permeability lies within tol
+    (relative) of k_ref, or None: the time to a permeability estimate within
+    1 % of the plain solver's converged one."""
+    for steps, _res, k, secs in history:
+        if abs(k - k_ref) < tol * abs(k_ref):
+            return steps, secs
+    return None

@@ -102,6 +102,13 @@ def test_workspace_size_and_validation(lib):
     p = _params(); p.nx, p.ny, p.nz = 1 << 15, 1 << 14, 1; bad.append(p)  # plane of 2^29 nodes
     for p in bad:
         assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -1
+    # valid but not provided: central moments beyond one D2Q9 component, the
+    # surface-tension source outside D2Q9 MRT
+    unsup = []
+    p = _params(collision="CLBM"); unsup.append(p)            # D3Q19
+    p = _params(); p.kappa[0] = 0.5; unsup.append(p)           # D3Q19
+    for p in unsup:
+        assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -2
 
 
 def test_init_rejects_bad_host_fields_before_touching_the_gpu(lib):

@@ -391,6 +391,29 @@ def test_surface_tension_table2_on_gpu():
     assert abs(sig[0.99] / sig[0.0] - 0.0091) < 0.05
 
 
+# ------------------------------------------ central-moment collision (D2Q9 CLBM)
+CLBM_RATES = (1.0, 1.4, 1.2, 1.0, 1.6, 1.0, 1.6, 1.25, 1.25)
+
+
+@pytest.mark.parametrize("storage,tol", [("F64", 1e-10), ("F32", 1e-4)])
+def test_central_moment_collision_d2q9(oracle_mod, storage, tol):
+    """Central moments with the consistent forcing (Eq. 3, Eq. 7-8) on a drop
+    resting on a wall under a body force: the interaction force, the wall's
+    virtual density and the body force all enter through R.  T_r = 0.9: with
+    the Zhang-Chen weight calibrated for exact-difference forcing, this forcing
+    runs the drop unstable at T_r = 0.7 (in the oracle as on the GPU)."""
+    c = inputs.load_coexistence()["CS"]["0.9"]
+    shape = (1, 45, 70)
+    w = inputs.Workload("clbm2d", "D2Q9", shape, collision="CLBM", storage=storage, tau=(0.8, 0.8),
+                        mrt_s=(CLBM_RATES, CLBM_RATES), eos_T=(c["T"],) * 2, A=(c["A"],) * 2,
+                        wet_mode=("PHI", "PHI"), wet=(1.1, 1.1), rho_min=(c["rho_v"],) * 2,
+                        rho_max=(c["rho_l"],) * 2, body=(2e-6, -1e-6, 0.0))
+    solid = inputs.walls(shape, "y", (0,))
+    rho = inputs.droplet(shape, (35.0, 1.0, 0.0), 14, 4, c["rho_l"], c["rho_v"])[None]
+    out, _, _ = run_pair(oracle_mod, w, solid, rho, 300)
+    assert_tol(out, tol)
+
+
 # ------------------------------------------------------- 16-bit deviation storage
 @pytest.mark.parametrize("storage", ["F16DEV", "BF16DEV"])
 def test_deviation_storage_error_is_reported(oracle_mod, storage):

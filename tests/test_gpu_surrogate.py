@@ -209,8 +209,11 @@ def test_training_reduces_the_loss(T, ops):
 def test_trained_network_gains_over_the_start_from_rest(T, ops):
     """Trained on a few solver-made 32^3 packs, the network's prediction of a
     held-out pack's steady velocity is much closer than the start from rest
-    (the zero field, relative error 1); its permeability estimate is close to
-    the solver's; and a warm start from it reaches the same permeability."""
+    (the zero field, relative error 1); a warm start from it has a
+    permeability within 1 % of the plain solver's converged one after fewer
+    steps than the start from rest, and converges to the same permeability.
+    Under the residual rule (r < 1e-6) the warm start is not faster here
+    either; the steps of both rules are reported."""
     from paper_2506_17713_amd import inputs
     from paper_2506_17713_amd.surrogate import (Surrogate, calibrate_flow, make_dataset, solve_steady, targets_of,
                                                 train, warm_fields)
@@ -234,11 +237,16 @@ def test_trained_network_gains_over_the_start_from_rest(T, ops):
     err_k = abs(float(pred[0].mean()) - cold["k"]) / cold["k"]
     rho0, u0 = warm_fields(pred, solid, a)
     warm = solve_steady(solid, accel=a, u0=u0, rho0=rho0)
+    from paper_2506_17713_amd.surrogate import first_within
+
+    c1 = first_within(cold["history"], cold["k"])[0]
+    w1 = first_within(warm["history"], cold["k"])[0]
     print(f"velocity error {err_u:.3f}, k error {err_k:.3f} (gain {gain:.3f}; uncalibrated "
-          f"{abs(k_raw - cold['k']) / cold['k']:.3f}), steps cold {cold['steps']} / {cold['k_steps']} "
-          f"warm {warm['steps']} / {warm['k_steps']} (residual rule / k rule)")
+          f"{abs(k_raw - cold['k']) / cold['k']:.3f}), steps cold {cold['steps']} / {cold['k_steps']} / {c1} "
+          f"warm {warm['steps']} / {warm['k_steps']} / {w1} (residual rule / k rule / within 1 %)")
     assert err_u < 0.6
     assert err_k < 0.3
+    assert w1 < c1
     assert abs(warm["k"] - cold["k"]) < 1e-3 * cold["k"]
 
 
