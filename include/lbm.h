@@ -42,7 +42,8 @@ typedef enum lbm_error {
     LBM_ERR_UNSUPPORTED = -2, /* valid but not provided by this library       */
     LBM_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed   */
     LBM_ERR_NONFINITE = -4,   /* a check found a non-finite or negative rho   */
-    LBM_ERR_SPACE = -5        /* workspace smaller than lbm_workspace_size   */
+    LBM_ERR_SPACE = -5,       /* workspace smaller than lbm_workspace_size   */
+    LBM_ERR_OOM = -6          /* host memory for the handle could not be had */
 } lbm_error;
 
 enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
@@ -129,7 +130,9 @@ typedef struct lbm_handle lbm_handle;
  * Errors: LBM_ERR_ARG for an invalid parameter set. */
 int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
 
-/* Create a handle and set the populations to the equilibrium of rho0/u0.
+/* Create a handle and set the populations to the equilibrium of rho0/u0
+ * (Eq. 3 with the moments given; the initial state of the droplet, slab and
+ * pore-filling runs of Sec. 3).
  *   p          parameters, copied.
  *   mask       host uint8[N], 1 = solid node (walls, grains), 0 = fluid.
  *   rho0       host double[n_comp][N], initial density per component.
@@ -144,7 +147,7 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
  *              (NULL = the null stream).
  * Synchronises the stream before returning.
  * Errors: LBM_ERR_ARG (bad parameters, NaN or negative rho0), LBM_ERR_SPACE,
- * LBM_ERR_UNSUPPORTED, LBM_ERR_HIP. */
+ * LBM_ERR_UNSUPPORTED, LBM_ERR_OOM, LBM_ERR_HIP. */
 int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const double* u0,
              const double* wet, void* workspace, size_t ws_bytes, void* stream,
              lbm_handle** out);
@@ -164,7 +167,10 @@ int lbm_step(lbm_handle* h, int64_t nsteps);
 int lbm_moments(lbm_handle* h, int comp, void* rho_dev, void* u_dev);
 
 /* Reduce the current state (FP64 accumulation, fixed order: bitwise
- * reproducible) and copy the result to *out.  Synchronises the stream.
+ * reproducible) and copy the result to *out: the masses of Eq. 4/10, the
+ * mixture momentum and mean u_x of Eq. 6 (Darcy permeability, Sec. 3.4.1),
+ * the saturation S_w of Sec. 3.4.3 and the steady-state residual.
+ * Synchronises the stream.
  * Returns LBM_ERR_NONFINITE if this or a latched periodic check saw a
  * non-finite or negative density (the latch is cleared). */
 int lbm_stats(lbm_handle* h, lbm_stats_t* out);

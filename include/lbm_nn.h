@@ -2,10 +2,11 @@
  * C-ABI of the convolutional surrogate kernels in liblbm.so.
  *
  * The surrogate is a 3-D encoder-decoder that maps a pore-space mask to the
- * steady single-phase velocity field; its prediction warm-starts the solver
- * (f = f^eq(1, u_pred)) when computing permeability from Darcy's law, the
- * workflow the paper runs with a cold start (Sec. 3.4.1, 50,000 steps to
- * steady state).  These are its training and inference kernels.
+ * steady single-phase velocity and pressure fields; its prediction
+ * warm-starts the solver (f = f^eq(rho_pred, u_pred - a/2), formed on the
+ * device by lbm_nn_warm_fields) when computing permeability from Darcy's
+ * law, the workflow the paper runs with a cold start (Sec. 3.4.1, 50,000
+ * steps to steady state).  These are its training and inference kernels.
  *
  * Conventions
  *   - Activations are FP32 device arrays [C][D][H][W] (W fastest).

@@ -33,6 +33,7 @@
  * branch (clamp, square-root argument test) is taken on the real part.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -709,6 +710,10 @@ void oref_collide_node(const oref_params *p, int k, const double *fin, const dou
 
 /* Populations f = f^eq(rho0, u0) at fluid nodes, zero at solid nodes.
  * rho0[nc][N]; u0[3][N] (shared by all components) or NULL for rest. */
+/* Threads of the parallel node loops (timing only: every node is computed
+ * independently, so the result does not depend on it). */
+void API(set_threads)(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 int API(init_feq)(const oref_params *p, const uint8_t *solid, const real_t *rho0,
                   const real_t *u0, real_t *f)
 {

@@ -157,6 +157,12 @@ def collide_node(w, k: int, fin, u, F) -> np.ndarray:
     return out
 
 
+def set_threads(n: int) -> None:
+    """Threads of the oracle's node loops (its results do not depend on it)."""
+    _lib(False).oref_set_threads(C.c_int(n))
+    _lib(True).orefc_set_threads(C.c_int(n))
+
+
 class State:
     """Oracle state of one run: populations f[nc, q, N] (post-streaming)."""
 

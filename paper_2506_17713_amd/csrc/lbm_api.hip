@@ -454,6 +454,7 @@ const char* lbm_strerror(int code) {
         case LBM_ERR_HIP: return "HIP runtime error";
         case LBM_ERR_NONFINITE: return "non-finite or negative density detected";
         case LBM_ERR_SPACE: return "workspace too small";
+        case LBM_ERR_OOM: return "out of host memory";
         default: return "unknown error";
     }
 }
@@ -492,7 +493,7 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
                 if (!std::isfinite(u0[d * N + n])) return LBM_ERR_ARG;
     }
     lbm_handle* h = new (std::nothrow) lbm_handle();
-    if (!h) return LBM_ERR_ARG;
+    if (!h) return LBM_ERR_OOM;
     h->p = *p;
     h->lay = lay;
     h->stream = (hipStream_t)stream;

@@ -26,7 +26,7 @@ from pathlib import Path
 
 import numpy as np
 
-_COEX = Path(__file__).resolve().parents[1] / "tests" / "golden" / "cs_coexistence.json"
+_COEX = Path(__file__).resolve().parent / "data" / "cs_coexistence.json"
 
 
 def load_coexistence() -> dict:

@@ -17,7 +17,7 @@ LIB_PATH = HERE / "_lib" / "liblbm.so"
 
 LBM_OK = 0
 ERRORS = {-1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP", -4: "LBM_ERR_NONFINITE",
-          -5: "LBM_ERR_SPACE"}
+          -5: "LBM_ERR_SPACE", -6: "LBM_ERR_OOM"}
 STORAGE = {"F64": 0, "F32": 1, "F16DEV": 2, "BF16DEV": 3, "F32F64": 4}
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_moments", "lbm_stats", "lbm_sync",
            "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_reset", "lbm_grad_workspace_size", "lbm_grad",

@@ -1,4 +1,8 @@
-"""Write tests/golden/cs_coexistence.json from the oracle alone.
+"""Write paper_2506_17713_amd/data/cs_coexistence.json from the oracle alone.
+
+The table holds workload parameters (coexistence densities, the force-mix
+weight A) that the input generators read; it is written here, beside the
+pins that check it, because only test code may run the oracle.
 
 For the Carnahan-Starling EOS with a = 1, b = 4, R = 1 (the paper's CS
 parameter set) this records, per reduced temperature T_r:
@@ -6,8 +10,8 @@ parameter set) this records, per reduced temperature T_r:
   * the Zhang-Chen weight A of the force mix (Eq. 11/13) calibrated on a 1-D
     flat liquid/vapour interface run with the FP64 oracle so that the steady
     vapour density equals the Maxwell value.  The paper states only that A
-    (and alpha) were "adjusted for each EOS" to satisfy mechanical stability
-    (Sec. 3.1); this is that adjustment, with alpha = 1;
+    (and alpha) were tuned per equation of state for mechanical stability
+    (Sec. 3.1); this is that tuning, with alpha = 1;
   * the liquid and vapour densities the oracle reaches with that A.
 
 Run:  python tests/golden/make_cs_coexistence.py
@@ -27,7 +31,7 @@ sys.path.insert(0, str(ROOT))
 from oracle import eos, oracle  # noqa: E402
 from paper_2506_17713_amd import inputs  # noqa: E402
 
-OUT = Path(__file__).resolve().parent / "cs_coexistence.json"
+OUT = ROOT / "paper_2506_17713_amd" / "data" / "cs_coexistence.json"
 NX, STEPS = 200, 30000
 
 

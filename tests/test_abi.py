@@ -134,6 +134,7 @@ def test_init_rejects_bad_host_fields_before_touching_the_gpu(lib):
 def test_strerror(lib):
     assert lib.lbm_strerror(0) == b"ok"
     assert b"workspace" in lib.lbm_strerror(-5)
+    assert b"memory" in lib.lbm_strerror(-6)
     assert lib.lbm_strerror(-99) == b"unknown error"
 
 
