@@ -19,12 +19,16 @@
  *      D2Q9 MRT optionally with the surface-tension source C    (Eq. 14-16);
  *      or the central-moment (cascaded) collision with the
  *      consistent forcing term of the same moments               (Eq. 3, Eq. 7-8)
- *   7. streaming with halfway bounce-back at solid nodes        (Eq. 2)
+ *   7. streaming with halfway bounce-back at solid nodes        (Eq. 2);
+ *      open boundaries: reservoir nodes at fixed density emit
+ *      their rest equilibrium (the constant-pressure inlet and
+ *      outlet of Sec. 3.4.3)
  * Macroscopic velocity output uses the half-force correction   (Eq. 6).
  *
  * State layout: f[(k*q + i)*N + n], n = (z*ny + y)*nx + x, x fastest; the
  * stored state is the post-streaming (pre-collision) population f(x, t).
- * Solid nodes carry no populations (their entries are kept at zero).
+ * Solid and reservoir nodes carry no populations (their entries are kept at
+ * zero).  Mask values: 0 fluid, 1 solid, 2 and 3 reservoirs 0 and 1.
  *
  * The same source is compiled twice: with real_t = double (symbols oref_*)
  * and with real_t = double _Complex (symbols orefc_*).  The complex build
@@ -73,7 +77,18 @@ typedef struct {
     double body[3];                    /* body acceleration                   */
     double rho_min[MAXC], rho_max[MAXC]; /* virtual-density limiter bounds    */
     double kappa[MAXC];                /* surface-tension adjustment (D2Q9 MRT) */
+    double res_rho[2][MAXC];           /* densities of reservoirs 0 and 1      */
 } oref_params;
+
+/* Node kinds of the mask: fluid, solid (bounce-back wall or grain), and two
+ * reservoirs.  A reservoir node is an open boundary held at fixed component
+ * densities res_rho[r][k] and at rest: it emits the rest equilibrium
+ * f^eq(res_rho, 0) into its fluid neighbours, and enters their force gather
+ * and the virtual densities of solids with psi(res_rho), like fluid.  It is
+ * not itself updated. */
+#define NODE_FLUID 0
+#define NODE_SOLID 1
+#define IS_RES(v) ((v) >= 2)
 
 /* ------------------------------------------------------------------------ */
 /* Lattice tables built from the definition of the velocity sets.           */
@@ -354,7 +369,8 @@ static void fields(const oref_params *p, const geom_t *G, const uint8_t *solid,
     for (long n = 0; n < N; ++n) {
         for (int k = 0; k < nc; ++k) {
             real_t r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-            if (!solid[n])
+            if (IS_RES(solid[n])) r = p->res_rho[solid[n] - 2][k];
+            if (solid[n] == NODE_FLUID)
                 for (int i = 0; i < q; ++i) {
                     real_t fi = f[((long)k * q + i) * N + n];
                     r += fi;
@@ -371,21 +387,22 @@ static void fields(const oref_params *p, const geom_t *G, const uint8_t *solid,
 
     /* 2. Improved virtual density (Eq. 17) at solid nodes with a fluid
      * neighbour: weighted average of fluid-neighbour densities, scaled by
-     * phi or shifted by -drho, then limited to [rho_min, rho_max]. */
+     * phi or shifted by -drho, then limited to [rho_min, rho_max].  A
+     * reservoir neighbour counts as fluid. */
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
         W->active[n] = 0;
-        if (!solid[n]) continue;
+        if (solid[n] != NODE_SOLID) continue;
         double den = 0.0;
         for (int i = 1; i < q; ++i)
-            if (!solid[G->nbr[i * N + n]]) den += L->w[i];
+            if (solid[G->nbr[i * N + n]] != NODE_SOLID) den += L->w[i];
         if (den == 0.0) continue;
         W->active[n] = 1;
         for (int k = 0; k < nc; ++k) {
             real_t num = 0.0;
             for (int i = 1; i < q; ++i) {
                 int m = G->nbr[i * N + n];
-                if (!solid[m]) num += L->w[i] * W->rho[(long)k * N + m];
+                if (solid[m] != NODE_SOLID) num += L->w[i] * W->rho[(long)k * N + m];
             }
             real_t rave = num / den;
             real_t prm = wet[(long)k * N + n];
@@ -396,12 +413,12 @@ static void fields(const oref_params *p, const geom_t *G, const uint8_t *solid,
         }
     }
 
-    /* 3. psi^k, U^k at fluid nodes and active solids (Eq. 12). */
+    /* 3. psi^k, U^k at fluid nodes, reservoirs and active solids (Eq. 12). */
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n)
         for (int k = 0; k < nc; ++k) {
             real_t ps = 0.0, uu = 0.0;
-            if (!solid[n] || W->active[n])
+            if (solid[n] != NODE_SOLID || W->active[n])
                 pseudopotential(p, k, W->rho[(long)k * N + n], &ps, &uu);
             W->psi[(long)k * N + n] = ps;
             W->U[(long)k * N + n] = uu;
@@ -413,7 +430,7 @@ static void fields(const oref_params *p, const geom_t *G, const uint8_t *solid,
     for (long n = 0; n < N; ++n)
         for (int k = 0; k < nc; ++k) {
             real_t Fk[3] = {0.0, 0.0, 0.0};
-            if (!solid[n]) {
+            if (solid[n] == NODE_FLUID) {
                 real_t zc[3] = {0.0, 0.0, 0.0}, sc[3] = {0.0, 0.0, 0.0};
                 for (int i = 1; i < q; ++i) {
                     int m = G->nbr[i * N + n];
@@ -446,7 +463,7 @@ static void fields(const oref_params *p, const geom_t *G, const uint8_t *solid,
     for (long n = 0; n < N; ++n)
         for (int k = 0; k < nc; ++k) {
             real_t Qxx = 0.0, Qyy = 0.0, Qxy = 0.0;
-            if (p->kappa[k] != 0.0 && !solid[n]) {
+            if (p->kappa[k] != 0.0 && solid[n] == NODE_FLUID) {
                 real_t ps = W->psi[(long)k * N + n];
                 real_t s_xx = 0.0, s_yy = 0.0, s_xy = 0.0, t_xx = 0.0, t_yy = 0.0, t_xy = 0.0;
                 for (int i = 1; i < q; ++i) {
@@ -522,7 +539,7 @@ static void collide(const oref_params *p, const geom_t *G, const uint8_t *solid,
     const int q = L->q, nc = p->nc;
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
-        if (solid[n]) {
+        if (solid[n] != NODE_FLUID) {
             for (int k = 0; k < nc; ++k)
                 for (int i = 0; i < q; ++i) fpost[((long)k * q + i) * N + n] = 0.0;
             continue;
@@ -600,7 +617,9 @@ static void collide(const oref_params *p, const geom_t *G, const uint8_t *solid,
 }
 
 /* 7. Streaming (Eq. 2) with halfway bounce-back: a population that would
- * leave a fluid node toward a solid node returns to it reversed. */
+ * leave a fluid node toward a solid node returns to it reversed; one that
+ * comes from a reservoir node is the reservoir's rest equilibrium
+ * w_i res_rho. */
 static void stream(const oref_params *p, const geom_t *G, const uint8_t *solid,
                    const real_t *fpost, real_t *f)
 {
@@ -612,10 +631,15 @@ static void stream(const oref_params *p, const geom_t *G, const uint8_t *solid,
         for (int k = 0; k < nc; ++k)
             for (int i = 0; i < q; ++i) {
                 real_t v = 0.0;
-                if (!solid[n]) {
+                if (solid[n] == NODE_FLUID) {
                     int src = G->nbr[L->opp[i] * N + n]; /* n - e_i */
-                    v = solid[src] ? fpost[((long)k * q + L->opp[i]) * N + n]
-                                   : fpost[((long)k * q + i) * N + src];
+                    if (solid[src] == NODE_SOLID)
+                        v = fpost[((long)k * q + L->opp[i]) * N + n];
+                    else if (IS_RES(solid[src]))
+                        v = 2.0 * L->w[i] * p->res_rho[solid[src] - 2][k] -
+                            fpost[((long)k * q + L->opp[i]) * N + n];
+                    else
+                        v = fpost[((long)k * q + i) * N + src];
                 }
                 f[((long)k * q + i) * N + n] = v;
             }
@@ -717,18 +741,20 @@ void API(set_threads)(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int API(init_feq)(const oref_params *p, const uint8_t *solid, const real_t *rho0,
                   const real_t *u0, real_t *f)
 {
-    lattice_t L;
-    build_lattice(p->lattice, &L);
-    long N = (long)p->nx * p->ny * p->nz;
+    geom_t G;
+    if (geom_init(p, &G)) return -2;
+    const lattice_t *L = &G.L;
+    const long N = G.N;
     for (long n = 0; n < N; ++n)
         for (int k = 0; k < p->nc; ++k) {
             real_t u[3] = {0.0, 0.0, 0.0}, fe[MAXQ];
             if (u0)
                 for (int d = 0; d < 3; ++d) u[d] = u0[(long)d * N + n];
-            feq(&L, rho0[(long)k * N + n], u, fe);
-            for (int i = 0; i < L.q; ++i)
-                f[((long)k * L.q + i) * N + n] = solid[n] ? 0.0 : fe[i];
+            feq(L, rho0[(long)k * N + n], u, fe);
+            for (int i = 0; i < L->q; ++i)
+                f[((long)k * L->q + i) * N + n] = solid[n] != NODE_FLUID ? 0.0 : fe[i];
         }
+    geom_free(&G);
     return 0;
 }
 
@@ -741,6 +767,8 @@ int API(step)(const oref_params *p, const uint8_t *solid, const real_t *wet, rea
     work_t W;
     double M[MAXQ][MAXQ], Mi[MAXQ][MAXQ];
     if (p->nc < 1 || p->nc > MAXC) return -1;
+    for (long n = 0; n < (long)p->nx * p->ny * p->nz; ++n)
+        if (solid[n] > 3) return -5;
     for (int k = 0; k < p->nc; ++k)
         if (p->kappa[k] != 0.0 && (p->lattice != 0 || p->collision != 1)) return -4;
     if (p->collision == 2 && p->nc != 1) return -4;
@@ -765,7 +793,8 @@ int API(step)(const oref_params *p, const uint8_t *solid, const real_t *wet, rea
 }
 
 /* Diagnostic fields of the current state (any output may be NULL):
- *   rho[nc][N]     density (virtual density at boundary solids, 0 elsewhere)
+ *   rho[nc][N]     density (virtual density at boundary solids, the fixed
+ *                  density at reservoirs, 0 at other solids)
  *   F[nc][3][N]    force on each component
  *   u[nc][3][N]    per-component velocity (j^k + F^k/2)/rho^k      (Eq. 6)
  *   umix[3][N]     mixture velocity sum_k(j^k + F^k/2)/sum_k rho^k
@@ -792,14 +821,14 @@ int API(fields)(const oref_params *p, const uint8_t *solid, const real_t *wet,
             real_t r = W.rho[(long)k * N + n];
             for (int d = 0; d < 3; ++d) {
                 real_t m = W.j[((long)k * 3 + d) * N + n] + 0.5 * W.F[((long)k * 3 + d) * N + n];
-                if (u) u[((long)k * 3 + d) * N + n] = solid[n] ? 0.0 : m / r;
+                if (u) u[((long)k * 3 + d) * N + n] = solid[n] != NODE_FLUID ? 0.0 : m / r;
                 num[d] += m;
             }
             den += r;
         }
         if (umix)
-            for (int d = 0; d < 3; ++d) umix[(long)d * N + n] = solid[n] ? 0.0 : num[d] / den;
-        if (solid[n] && rho)
+            for (int d = 0; d < 3; ++d) umix[(long)d * N + n] = solid[n] != NODE_FLUID ? 0.0 : num[d] / den;
+        if (solid[n] == NODE_SOLID && rho)
             for (int k = 0; k < nc; ++k)
                 if (!W.active[n]) rho[(long)k * N + n] = 0.0;
     }

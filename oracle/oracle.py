@@ -56,6 +56,7 @@ class OrefParams(C.Structure):
         ("body", C.c_double * 3),
         ("rho_min", C.c_double * MAXC), ("rho_max", C.c_double * MAXC),
         ("kappa", C.c_double * MAXC),
+        ("res_rho", (C.c_double * MAXC) * 2),
     ]
 
 
@@ -98,6 +99,8 @@ def params_from(w, T_im: float | tuple = 0.0) -> OrefParams:
             p.g[k][kk] = w.g[k][kk]
         p.rho_min[k], p.rho_max[k] = w.rho_min[k], w.rho_max[k]
         p.kappa[k] = w.kappa[k]
+        for r in range(2):
+            p.res_rho[r][k] = w.res_rho[r][k]
     for d in range(3):
         p.body[d] = w.body[d]
     return p
@@ -218,5 +221,57 @@ class State:
         fn(C.byref(self.p), _ptr(self.solid), _ptr(fpost), _ptr(out))
         return out
 
+    def set_reservoir(self, r: int, rho) -> None:
+        """New fixed densities (one per component) of reservoir r from the next step on."""
+        self.w = self.w.with_(res_rho=tuple(tuple(rho) if i == r else self.w.res_rho[i] for i in range(2)))
+        for k in range(self.w.nc):
+            self.p.res_rho[r][k] = float(rho[k])
+
     def mass(self) -> np.ndarray:
         return self.f.sum(axis=(1, 2))
+
+
+# --------------------------------------------------------------------------
+# In-situ capillary pressure and saturation (Sec. 3.4.3).
+# --------------------------------------------------------------------------
+def pressure(w, fld: dict) -> np.ndarray:
+    """Bulk pressure of the Shan-Chen fluid at every node,
+    p = c_s^2 sum_k rho^k + (1/2) sum_kk' g_kk' psi^k psi^k' (the pressure of
+    the interaction force of Eq. 13; with one component and the EOS
+    pseudopotential of Eq. 12 it equals alpha p_EOS(rho))."""
+    rho, psi = fld["rho"], fld["psi"]
+    p = rho.sum(axis=0) / 3.0
+    for k in range(w.nc):
+        for kk in range(w.nc):
+            p = p + 0.5 * w.g[k][kk] * psi[k] * psi[kk]
+    return p
+
+
+def capillary(w, solid: np.ndarray, fld: dict, window=None) -> dict:
+    """Capillary pressure and wetting saturation measured in place
+    (Sec. 3.4.3): over the fluid nodes of the planes window[0] <= c <
+    window[1] of the slowest lattice axis (z in 3-D, y in 2-D; all planes
+    when window is None), a node is non-wetting where rho^0 >= rho^1 (two
+    components; component 0 is the non-wetting fluid) or, for one
+    component, where rho lies below (rho_min + rho_max)/2 (vapour).
+    P_c = mean pressure of the non-wetting nodes - mean pressure of the
+    wetting nodes; S_w = wetting nodes / fluid nodes."""
+    nz, ny, nx = w.shape
+    plane = nx * ny if w.lattice == "D3Q19" else nx
+    n = np.arange(w.N)
+    c = n // plane
+    sel = solid.reshape(-1) == 0
+    if window is not None and window[1] > window[0]:
+        sel &= (c >= window[0]) & (c < window[1])
+    rho = fld["rho"]
+    if w.nc > 1:
+        nw = rho[0] >= rho[1]
+    else:
+        nw = rho[0] < 0.5 * (w.rho_min[0] + w.rho_max[0])
+    p = pressure(w, fld)
+    a, b = sel & nw, sel & ~nw
+    n_nw, n_w = int(a.sum()), int(b.sum())
+    p_nw = float(p[a].mean()) if n_nw else 0.0
+    p_w = float(p[b].mean()) if n_w else 0.0
+    return {"p_nw": p_nw, "p_w": p_w, "p_c": p_nw - p_w, "s_w": n_w / max(n_nw + n_w, 1),
+            "n_nw": n_nw, "n_w": n_w}

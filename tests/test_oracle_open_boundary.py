@@ -1,0 +1,181 @@
+"""Pins of the oracle's open boundaries and of the in-situ capillary-pressure
+and saturation measurement (Sec. 3.4.3).
+
+A reservoir node (mask 2 or 3) holds fixed component densities; a population
+that would stream in from it is the anti-bounce-back value 2 w_i rho_res -
+f*_opp(i)(x), which fixes the density, and so the pressure, halfway between
+the reservoir and the first fluid plane.  The pins: a reservoir at the fluid's
+own density and rest leaves the state unchanged; a closed tube fills to the
+reservoir density; two reservoirs at different densities drive the
+Poiseuille flow of the pressure gradient they set up, with that gradient
+reaching the imposed densities at the halfway planes; the mixture pressure
+is alpha p_EOS for one component and equal in the two bulks of a flat
+two-component interface; the capillary measurement of a state with known
+phases gives its volume fraction and pressure difference."""
+import numpy as np
+import pytest
+
+from oracle import eos
+from paper_2506_17713_amd import inputs
+from paper_2506_17713_amd.inputs import Workload
+
+COEX = inputs.load_coexistence()["CS"]
+IDEAL = dict(psi_kind=("DENSITY", "DENSITY"), g=((0.0, 0.0), (0.0, 0.0)))
+
+
+def channel_2d(nx, ny, res=(2, 3)):
+    """Channel along y between the halfway walls of a solid column x = 0
+    (periodic in x, so the column bounds both sides); row y = 0 is reservoir
+    res[0], row y = ny - 1 reservoir res[1] (1: a solid end)."""
+    mask = np.zeros((1, ny, nx), np.uint8)
+    mask[0, :, 0] = 1
+    mask[0, 0, :] = res[0]
+    mask[0, ny - 1, :] = res[1]
+    return mask
+
+
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+def test_reservoir_at_the_fluid_state_is_a_fixed_point(oracle_mod, lat):
+    if lat == "D2Q9":
+        shape = (1, 20, 12)
+        mask = channel_2d(12, 20)
+    else:
+        shape = (12, 8, 9)
+        mask = np.zeros(shape, np.uint8)
+        mask[:, 0, :] = 1
+        mask[0], mask[-1] = 2, 3
+    w = Workload("rest", lat, shape, tau=(0.8, 0.8), res_rho=((1.0, 1.0), (1.0, 1.0)), **IDEAL)
+    st = oracle_mod.State(w, mask, np.ones((1,) + shape))
+    f0 = st.f.copy()
+    st.step(200)
+    assert np.abs(st.f - f0).max() < 1e-14
+
+
+def test_closed_tube_fills_to_the_reservoir_density(oracle_mod):
+    # reservoir at one end, wall at the other: at rest the first fluid node's
+    # anti-bounce-back fixes rho = rho_res, so the tube ends up uniform at it
+    nx, ny = 8, 24
+    mask = channel_2d(nx, ny, res=(2, 1))
+    w = Workload("fill", "D2Q9", (1, ny, nx), tau=(1.0, 1.0), res_rho=((1.02, 1.02), (0.0, 0.0)), **IDEAL)
+    st = oracle_mod.State(w, mask, np.ones((1, 1, ny, nx)))
+    st.step(12000)
+    rho = st.fields()["rho"][0][mask.reshape(-1) == 0]
+    assert np.abs(rho - 1.02).max() < 1e-7
+    assert np.abs(st.fields()["umix"]).max() < 1e-9
+
+
+def _pressure_channel(oracle_mod, ny, drho, nx=22, tau=0.8, steps=12000):
+    rin, rout = 1.0 + 0.5 * drho, 1.0 - 0.5 * drho
+    mask = channel_2d(nx, ny)
+    w = Workload("pois", "D2Q9", (1, ny, nx), tau=(tau, tau), res_rho=((rin, rin), (rout, rout)), **IDEAL)
+    st = oracle_mod.State(w, mask, np.ones((1, 1, ny, nx)))
+    st.step(steps)
+    fld = st.fields()
+    r = fld["rho"][0].reshape(ny, nx)
+    uy = fld["umix"][1].reshape(ny, nx)
+    ys = np.arange(ny // 4, 3 * ny // 4)
+    fit = np.polyfit(ys, r[ys, nx // 2] / 3.0, 1)
+    # interior drop extrapolated to the halfway planes y = 1/2 and
+    # y = ny - 3/2, as a fraction of the imposed one
+    ratio = (np.polyval(fit, 0.5) - np.polyval(fit, ny - 1.5)) * 3.0 / drho
+    return r, uy, -fit[0], ratio
+
+
+def test_pressure_driven_poiseuille(oracle_mod):
+    nx, ny, tau = 22, 80, 0.8
+    r, uy, G, _ = _pressure_channel(oracle_mod, ny, 0.004, nx=nx, tau=tau)
+    # steady mass flux, equal through every row
+    flux = (r * uy)[1:-1].sum(axis=1)
+    assert np.ptp(flux) < 1e-8 * flux.mean()
+    # the pressure gradient of the middle half drives plane Poiseuille flow
+    # between the halfway walls x = 1/2 and x = nx - 1/2 (width nx - 1)
+    nu = (tau - 0.5) / 3.0
+    H = nx - 1
+    xs = np.arange(1, nx) - 0.5 * nx  # distance from the channel centre
+    prof = G / (2.0 * r[ny // 2, 1:].mean() * nu) * (H * H / 4.0 - xs ** 2)
+    assert np.abs(uy[ny // 2, 1:] - prof).max() < 3e-3 * prof.max()
+
+
+def test_reservoir_pressures_are_reached_as_the_channel_grows(oracle_mod):
+    # the interior gradient, extrapolated to the halfway planes, spans the
+    # imposed density difference up to an end loss of fixed size in lattice
+    # units (about 1.3 nodes in all): its share halves when the channel
+    # doubles in length, and does not depend on the flow speed
+    r80 = _pressure_channel(oracle_mod, 80, 0.001, steps=20000)[3]
+    r160 = _pressure_channel(oracle_mod, 160, 0.001, steps=40000)[3]
+    r80f = _pressure_channel(oracle_mod, 80, 0.004, steps=20000)[3]
+    assert abs(r160 - 1.0) < 0.02
+    assert 1.8 < (r80 - 1.0) / (r160 - 1.0) < 2.3
+    assert abs(r80f - r80) < 2e-3
+
+
+@pytest.mark.parametrize("tr", ["0.7", "0.9"])
+def test_pressure_is_alpha_p_eos_for_one_component(oracle_mod, tr):
+    e = COEX[tr]
+    shape = (1, 4, 4)
+    w = Workload("p", "D2Q9", shape, eos_T=(e["T"], e["T"]), A=(e["A"], e["A"]))
+    for rho in (e["rho_v"], 0.5 * (e["rho_v"] + e["rho_l"]), e["rho_l"]):
+        st = oracle_mod.State(w, np.zeros(shape, np.uint8), np.full((1,) + shape, rho))
+        p = oracle_mod.pressure(w, st.fields())
+        want = eos.CS.pressure(rho, e["T"])
+        assert np.allclose(p, want, rtol=1e-12, atol=1e-15)
+
+
+def test_two_component_pressure_balances_across_a_flat_interface(oracle_mod):
+    # unequal self-interactions make the two bulks different; at mechanical
+    # equilibrium of a flat interface their pressures still agree
+    n = 64
+    shape = (1, 4, n)
+    g = ((-0.05, 0.6), (0.6, 0.0))
+    w = Workload("flat2", "D2Q9", shape, nc=2, tau=(1.0, 1.0), psi_kind=("DENSITY", "DENSITY"), g=g)
+    front = inputs.slab(shape, "x", n // 4, 3 * n // 4, 3.0, 1.0, 0.0)
+    rho = np.stack([0.05 + 0.95 * front, 0.05 + 0.9 * (1.0 - front)])
+    st = oracle_mod.State(w, np.zeros(shape, np.uint8), rho)
+    st.step(8000)
+    fld = st.fields()
+    p = oracle_mod.pressure(w, fld).reshape(shape)[0, 0]
+    r = fld["rho"].reshape((2,) + shape)[:, 0, 0]
+    assert abs(r[0, n // 2] - r[0, 0]) > 0.5  # two distinct bulks
+    assert abs(p[n // 2] - p[0]) < 1e-5 * abs(p[0])
+
+
+def test_capillary_measure_of_a_two_phase_state(oracle_mod):
+    # initial state with a sharp boundary: component 0 (non-wetting) fills
+    # x < 10 of a 24-wide box, the rest is wetting; each half is uniform, so
+    # the measurement returns the volume fraction and the difference of the
+    # two bulk pressures
+    shape = (6, 5, 24)
+    g = ((-0.027, 0.57), (0.57, -0.027))
+    w = Workload("cap", "D3Q19", shape, nc=2, psi_kind=("DENSITY", "DENSITY"), g=g)
+    x = np.arange(24)[None, None, :] * np.ones(shape)
+    nw = x < 10
+    rho = np.stack([np.where(nw, 0.9, 0.03), np.where(nw, 0.05, 1.0)])
+    mask = np.zeros(shape, np.uint8)
+    mask[:, :, 20] = 1  # a solid wall plane is not counted
+    st = oracle_mod.State(w, mask, rho)
+    cap = oracle_mod.capillary(w, mask, st.fields())
+    assert cap["n_nw"] == 10 * 30 and cap["n_w"] == 13 * 30
+    assert cap["s_w"] == pytest.approx(13 / 23, abs=1e-15)
+
+    def bulk(r0, r1):
+        return (r0 + r1) / 3.0 + 0.5 * (g[0][0] * r0 * r0 + 2 * g[0][1] * r0 * r1 + g[1][1] * r1 * r1)
+
+    assert cap["p_c"] == pytest.approx(bulk(0.9, 0.05) - bulk(0.03, 1.0), rel=1e-12)
+    # a window of planes z in [2, 4)
+    cap2 = oracle_mod.capillary(w, mask, st.fields(), window=(2, 4))
+    assert cap2["n_nw"] == 10 * 10 and cap2["n_w"] == 13 * 10
+
+
+def test_one_component_capillary_classes_vapour_as_non_wetting(oracle_mod):
+    e = COEX["0.8"]
+    shape = (1, 10, 10)
+    w = Workload("v", "D2Q9", shape, eos_T=(e["T"],) * 2, A=(e["A"],) * 2, rho_min=(e["rho_v"],) * 2,
+                 rho_max=(e["rho_l"],) * 2)
+    rho = np.full((1,) + shape, e["rho_l"])
+    rho[0, 0, :3] = e["rho_v"]
+    st = oracle_mod.State(w, np.zeros(shape, np.uint8), rho)
+    cap = oracle_mod.capillary(w, np.zeros(shape, np.uint8), st.fields())
+    assert cap["n_nw"] == 30 and cap["s_w"] == pytest.approx(0.7)
+    pv = eos.CS.pressure(e["rho_v"], e["T"])
+    pl = eos.CS.pressure(e["rho_l"], e["T"])
+    assert cap["p_c"] == pytest.approx(pv - pl, rel=1e-10, abs=1e-14)
