@@ -10,8 +10,9 @@
  *   Shan-Chen / Zhang-Chen interaction force            (Eq. 11, Eq. 13)
  *   BGK or MRT collision with exact-difference forcing  (Eq. 3, Eq. 5)
  *   streaming with halfway bounce-back                  (Eq. 1, Eq. 2)
+ *   open boundaries: reservoirs at fixed density        (Sec. 3.4.3)
  * and observes densities and velocities with the half-force correction
- * (Eq. 6).
+ * (Eq. 6), and in place the capillary pressure and saturation (Sec. 3.4.3).
  *
  * Conventions
  *   - Every function returns LBM_OK (0) or a negative lbm_error code; no
@@ -105,6 +106,15 @@ typedef struct lbm_params {
                                    Q takes the factor g_kk, which the printed
                                    Eq. 16 leaves out.  0 = off; nonzero with
                                    D3Q19 or BGK: LBM_ERR_UNSUPPORTED           */
+    double res_rho[2][2];       /* res_rho[r][k]: fixed density of component k
+                                   in reservoir r (mask value 2 + r); > 0 for
+                                   every reservoir the mask uses               */
+    int32_t window[2];          /* planes window[0] <= c < window[1] of the
+                                   slowest axis (z; y in 2-D) over which
+                                   lbm_stats measures the capillary pressure
+                                   and wetting saturation; window[1] <=
+                                   window[0]: every plane                      */
+    int32_t reserved2[2];       /* must be zero                                */
 } lbm_params;
 
 typedef struct lbm_stats_t {
@@ -120,6 +130,14 @@ typedef struct lbm_stats_t {
     int64_t n_fluid;            /* number of fluid nodes                        */
     int32_t nonfinite;          /* count of fluid nodes with non-finite values  */
     int32_t negative;           /* count of fluid nodes with rho^k < 0          */
+    /* In-situ capillary pressure and saturation (Sec. 3.4.3) over the fluid
+     * nodes of the parameter window, each classed as for `saturation`;
+     * pressure p = c_s^2 sum_k rho^k + (1/2) sum_kk' g_kk' psi^k psi^k'
+     * (alpha p_EOS for one component with the EOS pseudopotential). */
+    double p_nonwetting;        /* mean p over the non-wetting nodes (0: none)  */
+    double p_wetting;           /* mean p over the wetting nodes (0: none)      */
+    double capillary_pressure;  /* p_nonwetting - p_wetting                     */
+    double s_wetting;           /* wetting nodes / fluid nodes of the window    */
 } lbm_stats_t;
 
 typedef struct lbm_handle lbm_handle;
@@ -134,7 +152,17 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
  * (Eq. 3 with the moments given; the initial state of the droplet, slab and
  * pore-filling runs of Sec. 3).
  *   p          parameters, copied.
- *   mask       host uint8[N], 1 = solid node (walls, grains), 0 = fluid.
+ *   mask       host uint8[N]: 0 = fluid, 1 = solid (walls, grains; halfway
+ *              bounce-back), 2 / 3 = reservoir 0 / 1.  A reservoir is an open
+ *              boundary (Sec. 3.4.3: constant-pressure inlet and outlet) held
+ *              at the densities p->res_rho[r] and at rest: a population that
+ *              would stream in from it is 2 w_i rho_res - f*_opp(i)(x) (anti-
+ *              bounce-back, which fixes the density halfway between the
+ *              reservoir and x), and its psi(rho_res) enters the force and
+ *              virtual densities of its neighbours.  Reservoir nodes must fill
+ *              whole planes of the slowest axis (z; y in 2-D), one reservoir
+ *              per plane, and no fluid node may touch reservoir planes on
+ *              both sides (LBM_ERR_ARG otherwise).
  *   rho0       host double[n_comp][N], initial density per component.
  *   u0         host double[3][N] initial equilibrium velocity j/rho (x, y, z),
  *              or NULL for rest.  The velocity of Eq. 6 reported by
@@ -178,6 +206,15 @@ int lbm_stats(lbm_handle* h, lbm_stats_t* out);
 /* Synchronise the stream; report a latched check failure or HIP error. */
 int lbm_sync(lbm_handle* h);
 
+/* New fixed densities rho[n_comp] (host) of reservoir r (0 or 1) from the
+ * next step on: the inlet or outlet pressure of a drainage or imbibition
+ * run, raised in stages to trace a capillary pressure - saturation curve
+ * (Sec. 3.4.3).  The populations that stream in during the next lbm_step
+ * and later take the new density; the current state (what lbm_moments and
+ * lbm_stats see before that step) keeps the old one.  Errors: LBM_ERR_ARG
+ * (r out of range, a density not finite and positive). */
+int lbm_set_reservoir(lbm_handle* h, int r, const double* rho);
+
 /* Restart from f = f^eq(rho0, u0) (Eq. 3 with the moments given), as
  * lbm_init does, but from device arrays: for callers whose initial fields
  * are computed on the GPU (a learned warm start).  rho0_dev [n_comp][N] and
@@ -211,9 +248,9 @@ int lbm_set_state(lbm_handle* h, const void* dev_src);
  *                       array dL_drho[N] of the compute type (any objective
  *                       linearised in the final density).
  * Supported for one component with LBM_STORE_F32 or LBM_STORE_F64, BGK or
- * MRT, and no surface-tension source; other configurations (two components,
- * 16-bit storage, LBM_STORE_F32_F64, kappa != 0, LBM_CLBM) return
- * LBM_ERR_UNSUPPORTED.
+ * MRT, no surface-tension source and no reservoirs; other configurations
+ * (two components, 16-bit storage, LBM_STORE_F32_F64, kappa != 0, LBM_CLBM,
+ * reservoir nodes) return LBM_ERR_UNSUPPORTED.
  * ------------------------------------------------------------------------ */
 enum { LBM_OBS_SATURATION = 0, LBM_OBS_DRHO = 1 };
 

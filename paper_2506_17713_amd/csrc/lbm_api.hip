@@ -51,6 +51,7 @@ int validate(const lbm_params* p) {
     if (p->check_every < 0) return LBM_ERR_ARG;
     for (int i = 0; i < 4; ++i)
         if (p->reserved[i] != 0) return LBM_ERR_ARG;
+    if (p->reserved2[0] != 0 || p->reserved2[1] != 0) return LBM_ERR_ARG;
     for (int k = 0; k < p->n_comp; ++k) {
         if (!(p->tau[k] > 0.5) || !std::isfinite(p->tau[k])) return LBM_ERR_ARG;
         if (p->psi_kind[k] != LBM_PSI_CS && p->psi_kind[k] != LBM_PSI_DENSITY) return LBM_ERR_ARG;
@@ -163,6 +164,10 @@ void fill_args(lbm_handle* h, StepArgs<R>& a, const Buffers* bufs) {
         a.rho_min[k] = (R)p.rho_min[k];
         a.rho_max[k] = (R)p.rho_max[k];
         a.kq[k] = (R)(p.kappa[k] * p.g[k][k]);
+        for (int r = 0; r < 2; ++r) {
+            a.res_rho[r][k] = (R)p.res_rho[r][k];
+            a.res_abb[r][k] = (R)h->res_active[r][k];
+        }
     }
     for (int d = 0; d < 3; ++d) a.body[d] = (R)p.body_accel[d];
 }
@@ -306,7 +311,9 @@ hipError_t run_kernel(lbm_handle* h, bool mom, int comp = -1, void* rho = nullpt
 // ---------------------------------------------------------------------------
 // Reductions (FP64 accumulators, wavefront shuffles, fixed order).
 // Slots: 0,1 mass; 2,3,4 momentum; 5 sum|ux-prev|; 6 sum|ux|; 7 sum ux;
-//        8 non-wetting count; 9 fluid count; 10 non-finite; 11 negative.
+//        8 non-wetting count; 9 fluid count; 10 non-finite; 11 negative;
+//        in the window of planes: 12 / 13 pressure sums of the non-wetting /
+//        wetting nodes, 14 / 15 their counts (Sec. 3.4.3).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -314,14 +321,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+constexpr int kSlotsUsed = 16;
+
 template <class R>
 __global__ void __launch_bounds__(kRedThreads)
     k_reduce1(const R* __restrict__ rho, const R* __restrict__ u, R* __restrict__ uxprev,
               const uint32_t* __restrict__ nbr, double* __restrict__ partial, int N, int nc,
-              int have_prev, R rho_mid) {
-    double acc[12];
+              int have_prev, R rho_mid, StepArgs<R> P, int plane, int w0, int w1) {
+    double acc[kSlotsUsed];
 #pragma unroll
-    for (int s = 0; s < 12; ++s) acc[s] = 0.0;
+    for (int s = 0; s < kSlotsUsed; ++s) acc[s] = 0.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
         if (nbr[n] & 1u) continue;
         const double r0 = rho[n];
@@ -338,22 +347,35 @@ __global__ void __launch_bounds__(kRedThreads)
         acc[5] += fabs(ux - prev);
         acc[6] += fabs(ux);
         acc[7] += ux;
-        acc[8] += nc > 1 ? (r0 >= r1 ? 1.0 : 0.0) : (r0 < (double)rho_mid ? 1.0 : 0.0);
+        const bool nw = nc > 1 ? r0 >= r1 : r0 < (double)rho_mid;
+        acc[8] += nw ? 1.0 : 0.0;
         acc[9] += 1.0;
+        const int c = n / plane;
+        if (c >= w0 && c < w1) {
+            // p = c_s^2 sum_k rho^k + (1/2) sum_kk' g_kk' psi^k psi^k'
+            R ps0, ps1 = (R)0, U;
+            psi_of(P, 0, (R)r0, ps0, U);
+            if (nc > 1) psi_of(P, 1, (R)r1, ps1, U);
+            const double s0 = ps0, s1 = ps1;
+            double pr = rt / 3.0 + 0.5 * (double)P.g[0][0] * s0 * s0;
+            if (nc > 1) pr += (double)P.g[0][1] * s0 * s1 + 0.5 * (double)P.g[1][1] * s1 * s1;
+            acc[nw ? 12 : 13] += pr;
+            acc[nw ? 14 : 15] += 1.0;
+        }
         const bool fin = std::isfinite(r0) && std::isfinite(r1) && std::isfinite(ux) && std::isfinite(uy) &&
                          std::isfinite(uz);
         acc[10] += fin ? 0.0 : 1.0;
         acc[11] += (r0 < 0.0 || r1 < 0.0) ? 1.0 : 0.0;
     }
-    __shared__ double sh[kRedThreads / 64][12];
+    __shared__ double sh[kRedThreads / 64][kSlotsUsed];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int s = 0; s < 12; ++s) {
+    for (int s = 0; s < kSlotsUsed; ++s) {
         const double v = wave_sum(acc[s]);
         if (lane == 0) sh[wv][s] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 12) {
+    if (threadIdx.x < kSlotsUsed) {
         double v = 0.0;
         for (int w = 0; w < kRedThreads / 64; ++w) v += sh[w][threadIdx.x];
         partial[(size_t)blockIdx.x * kStatSlots + threadIdx.x] = v;
@@ -363,7 +385,7 @@ __global__ void __launch_bounds__(kRedThreads)
 __global__ void k_reduce2(const double* __restrict__ partial, double* __restrict__ out, int nblk) {
     // one wavefront per slot, fixed order
     const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (s >= 12) return;
+    if (s >= kSlotsUsed) return;
     double v = 0.0;
     for (int b = lane; b < nblk; b += 64) v += partial[(size_t)b * kStatSlots + s];
     v = wave_sum(v);
@@ -389,22 +411,32 @@ hipError_t enqueue_stats(lbm_handle* h) {
     const double mid = 0.5 * (h->p.rho_min[0] + h->p.rho_max[0]);
     const uint32_t* nbr = reinterpret_cast<const uint32_t*>(ws + h->lay.nbr);
     double* part = reinterpret_cast<double*>(ws + h->lay.partial);
+    const int plane = h->NA * h->NB;
+    int w0 = h->p.window[0], w1 = h->p.window[1];
+    if (w1 <= w0) {
+        w0 = 0;
+        w1 = h->NCc;
+    }
     if (real_bytes(h->p.storage) == 8) {
+        StepArgs<double> a;
+        fill_args(h, a, nullptr);
         hipLaunchKernelGGL(k_reduce1<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream,
                            reinterpret_cast<const double*>(ws + h->lay.mrho),
                            reinterpret_cast<const double*>(ws + h->lay.mu),
                            reinterpret_cast<double*>(ws + h->lay.uxprev), nbr, part, h->N, h->p.n_comp,
-                           h->have_prev ? 1 : 0, mid);
+                           h->have_prev ? 1 : 0, mid, a, plane, w0, w1);
     } else {
+        StepArgs<float> a;
+        fill_args(h, a, nullptr);
         hipLaunchKernelGGL(k_reduce1<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, h->stream,
                            reinterpret_cast<const float*>(ws + h->lay.mrho),
                            reinterpret_cast<const float*>(ws + h->lay.mu),
                            reinterpret_cast<float*>(ws + h->lay.uxprev), nbr, part, h->N, h->p.n_comp,
-                           h->have_prev ? 1 : 0, (float)mid);
+                           h->have_prev ? 1 : 0, (float)mid, a, plane, w0, w1);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(12 * 64), 0, h->stream, part,
+    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(kSlotsUsed * 64), 0, h->stream, part,
                        reinterpret_cast<double*>(ws + h->lay.dstats), kRedBlocks);
     h->have_prev = true;
     return hipGetLastError();
@@ -422,10 +454,13 @@ hipError_t launch_init(lbm_handle* h, const void* rho0, const void* u0) {
     const int N = h->N;
     const int blk = 256, grid = (N + blk - 1) / blk;
     using R = typename Store<ST>::R;
+    ResRho res;
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 2; ++k) res.r[r][k] = h->res_active[r][k];
     hipLaunchKernelGGL((k_init<LAT, NC, ST>), dim3(grid), dim3(blk), 0, h->stream, (const R*)rho0,
                        (const R*)u0, reinterpret_cast<const uint32_t*>(h->ws + h->lay.nbr), h->ws + h->lay.fA,
                        is_dev(h->p.storage) ? reinterpret_cast<float*>(h->ws + h->lay.rA) : nullptr, h->NA,
-                       h->NB, h->NCc);
+                       h->NB, h->NCc, res);
     return hipGetLastError();
 }
 
@@ -478,6 +513,36 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     if (((uintptr_t)workspace & 255u) != 0) return LBM_ERR_ARG;
     const size_t N = (size_t)p->nx * p->ny * p->nz;
     const int nc = p->n_comp;
+    // open boundaries: reservoir nodes fill whole planes of the marching axis,
+    // one reservoir per plane, with positive densities, and no fluid plane
+    // lies between two reservoir planes
+    const size_t plane = (size_t)p->nx * (p->lattice == LBM_D2Q9 ? 1 : p->ny);
+    const size_t n_planes = N / plane;
+    std::vector<int> kind(n_planes, 0);  // 0 none, 1 fluid, 2 / 3 reservoir
+    bool has_res = false;
+    for (size_t c = 0; c < n_planes; ++c) {
+        const uint8_t* m = mask + c * plane;
+        const uint8_t m0 = m[0];
+        size_t nres = 0, nfl = 0;
+        for (size_t i = 0; i < plane; ++i) {
+            if (m[i] > 3) return LBM_ERR_ARG;
+            if (m[i] >= 2) {
+                if (m[i] != m0) return LBM_ERR_ARG;
+                ++nres;
+            }
+            if (m[i] == 0) ++nfl;
+        }
+        if (nres && nres != plane) return LBM_ERR_ARG;
+        kind[c] = nres ? m0 : (nfl ? 1 : 0);
+        if (nres) {
+            has_res = true;
+            for (int k = 0; k < nc; ++k)
+                if (!std::isfinite(p->res_rho[m0 - 2][k]) || !(p->res_rho[m0 - 2][k] > 0.0)) return LBM_ERR_ARG;
+        }
+    }
+    for (size_t c = 0; c < n_planes && has_res; ++c)
+        if (kind[c] == 1 && kind[(c + n_planes - 1) % n_planes] >= 2 && kind[(c + 1) % n_planes] >= 2)
+            return LBM_ERR_ARG;
     size_t n_solid = 0;
     for (size_t n = 0; n < N; ++n) {
         if (mask[n]) {
@@ -507,6 +572,8 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     h->since_check = 0;
     h->have_prev = false;
     h->wet_uniform = wet == nullptr;
+    h->has_res = has_res;
+    std::memcpy(h->res_active, p->res_rho, sizeof(h->res_active));
     h->mostly_fluid = n_solid * 10 < N;
     // LBM_CHUNK (environment, tuning only): planes per workgroup along the
     // marching axis; unset or 0 chooses about 2048 workgroups per launch.
@@ -578,6 +645,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps) {
     if (!h || nsteps < 0) return LBM_ERR_ARG;
     for (int64_t s = 0; s < nsteps; ++s) {
         if (run_kernel(h, false) != hipSuccess) return LBM_ERR_HIP;
+        std::memcpy(h->res_active, h->p.res_rho, sizeof(h->res_active));
         h->cur ^= 1;
         h->step += 1;
         if (h->p.check_every > 0 && ++h->since_check >= h->p.check_every) {
@@ -629,12 +697,26 @@ int lbm_stats(lbm_handle* h, lbm_stats_t* out) {
     out->n_fluid = (int64_t)r[9];
     out->nonfinite = (int32_t)r[10];
     out->negative = (int32_t)r[11];
+    out->p_nonwetting = r[14] > 0.0 ? r[12] / r[14] : 0.0;
+    out->p_wetting = r[15] > 0.0 ? r[13] / r[15] : 0.0;
+    out->capillary_pressure = out->p_nonwetting - out->p_wetting;
+    out->s_wetting = r[14] + r[15] > 0.0 ? r[15] / (r[14] + r[15]) : 0.0;
     return rc;
 }
 
 int lbm_sync(lbm_handle* h) {
     if (!h) return LBM_ERR_ARG;
     return read_flag(h, nullptr);
+}
+
+int lbm_set_reservoir(lbm_handle* h, int r, const double* rho) {
+    if (!h || !rho || r < 0 || r > 1) return LBM_ERR_ARG;
+    for (int k = 0; k < h->p.n_comp; ++k)
+        if (!std::isfinite(rho[k]) || !(rho[k] > 0.0)) return LBM_ERR_ARG;
+    // the populations of the next step stream in at this density; the pulls
+    // take it up after that step (res_active)
+    for (int k = 0; k < h->p.n_comp; ++k) h->p.res_rho[r][k] = rho[k];
+    return LBM_OK;
 }
 
 int lbm_state_bytes(const lbm_handle* h, size_t* bytes_out) {
@@ -675,6 +757,7 @@ int lbm_reset(lbm_handle* h, const void* rho0_dev, const void* u0_dev) {
     h->step = 0;
     h->since_check = 0;
     h->have_prev = false;
+    std::memcpy(h->res_active, h->p.res_rho, sizeof(h->res_active));
     const Layout& lay = h->lay;
     hipError_t e = hipMemsetAsync(h->ws + lay.dstats, 0, kStatSlots * 8 + 8, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + lay.fA, 0, lay.fB - lay.fA, h->stream);

@@ -348,7 +348,20 @@ struct StepArgs {
     R body[3];
     R rho_min[2], rho_max[2];
     R kq[2];               // surface-tension source (D2Q9 MRT): kappa_k g_kk
+    R res_rho[2][2];       // open boundaries: density of component k in reservoir r
+    R res_abb[2][2];       // ... in the inflow of the streaming the pull completes
 };
+
+// Neighbour-word bits above the direction bits (bit 0: the node is not
+// fluid; bit i: the source x - e_i is solid or a reservoir, so the pull takes
+// the node's own opposite population).  Reservoir nodes fill whole planes of
+// the marching axis c, so a fluid node next to one takes from it exactly the
+// directions with e_c = +1 (reservoir plane below) or e_c = -1 (above).
+constexpr uint32_t NW_RES_LO = 1u << 20;   // plane c - 1 is a reservoir
+constexpr uint32_t NW_RES_HI = 1u << 21;   // plane c + 1 is a reservoir
+constexpr uint32_t NW_RES_ID = 1u << 22;   // ... and it is reservoir 1
+constexpr uint32_t NW_OWN_RES = 1u << 23;  // the node is a reservoir node
+constexpr uint32_t NW_OWN_ID = 1u << 24;   // ... of reservoir 1
 
 __device__ __forceinline__ int wrap_near(int v, int n) {
     // v in [-n, 2n)
@@ -513,6 +526,38 @@ __device__ __forceinline__ void psi_of(const StepArgs<R>& P, int k, R rho, R& ps
         psi = rho;
         U = (R)0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Open boundary (anti-bounce-back): a population whose source is a reservoir
+// was pulled as the node's own opposite post-collision one, f*_opp(i)(x); it
+// becomes 2 w_i rho_res - f*_opp(i)(x), which holds the density halfway
+// between the reservoir and x at rho_res (the constant-pressure inlet and
+// outlet of Sec. 3.4.3).
+// ---------------------------------------------------------------------------
+template <int LAT, int NC, class R>
+__device__ __forceinline__ void open_fix(const StepArgs<R>& P, uint32_t word, R (&f)[NC][Lat<LAT>::Q]) {
+    using L = Lat<LAT>;
+    if (!(word & (NW_RES_LO | NW_RES_HI))) return;
+    const int side = (word & NW_RES_LO) ? 1 : -1;
+    const int id = (word & NW_RES_ID) ? 1 : 0;
+    sfor<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (L::ec(i) != 0) {
+            if (L::ec(i) == side) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) f[k][i] = (R)(2.0 * L::w(i)) * P.res_abb[id][k] - f[k][i];
+            }
+        }
+    });
+}
+
+// Density a non-fluid node shows its neighbours in the rho ring: a
+// reservoir's fixed density, else the solid marks (-1: its virtual density is
+// needed, -2: no fluid neighbour).
+template <class R>
+__device__ __forceinline__ R nonfluid_rho(const StepArgs<R>& P, uint32_t word, int k, R mark) {
+    return (word & NW_OWN_RES) ? P.res_rho[(word & NW_OWN_ID) ? 1 : 0][k] : mark;
 }
 
 // ---------------------------------------------------------------------------
@@ -773,8 +818,9 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
             if (!(wo & 1u)) rs_scale(fo, wo, (lb_own + 3) * SWA + la_own + 3, cp);
         if (wo & 1u) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = solid_mark(wo);
+            for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = nonfluid_rho(P, wo, k, solid_mark(wo));
         } else {
+            open_fix<LAT, NC>(P, wo, fo);
 #pragma unroll
             for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = rho_sum(fo, k);
         }
@@ -783,7 +829,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
             if (!h_on[j]) continue;
             if (wh[j] & 1u) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = solid_mark(wh[j]);
+                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = nonfluid_rho(P, wh[j], k, solid_mark(wh[j]));
             } else if (!need(j)) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = (R)0;  // never read
@@ -800,6 +846,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
                     const int rb = h_idx[j] / RWA;
                     rs_scale(f, wh[j], h_idx[j] + 2 * rb + SWA + 1, cp);
                 }
+                open_fix<LAT, NC>(P, wh[j], f);
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = rho_sum(f, k);
             }
@@ -1377,7 +1424,10 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
                 if (a < NA && b < NB) {
                     const int n = (it * NB + b) * NA + a;
                     const uint32_t word = P.nbr[n];
-                    if (!(word & 1u)) pull_node<LAT, ST, NC>(P, a, b, it, word, fc0);
+                    if (!(word & 1u)) {
+                        pull_node<LAT, ST, NC>(P, a, b, it, word, fc0);
+                        open_fix<LAT, NC>(P, word, fc0);
+                    }
                     collide_f(it, fc0, true, word);
                 }
             }
@@ -1397,7 +1447,9 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
 // ---------------------------------------------------------------------------
 // Initialisation kernels.
 // ---------------------------------------------------------------------------
-// Neighbour words: bit 0 = node solid, bit i = node n - e_i solid.
+// Neighbour words from the mask (0 fluid, 1 solid, 2 / 3 reservoir 0 / 1):
+// bit 0 = the node is not fluid, bit i = the node n - e_i is not fluid, and
+// the reservoir bits NW_*.
 template <int LAT>
 __global__ void k_nbr_words(const uint8_t* __restrict__ mask, uint32_t* __restrict__ nbr, int NA,
                             int NB, int NCc) {
@@ -1406,24 +1458,33 @@ __global__ void k_nbr_words(const uint8_t* __restrict__ mask, uint32_t* __restri
     const int N = NA * NB * NCc;
     if (n >= N) return;
     const int a = n % NA, b = (n / NA) % NB, c = n / (NA * NB);
-    uint32_t w = mask[n] ? 1u : 0u;
+    const uint32_t m0 = mask[n];
+    uint32_t w = m0 ? 1u : 0u;
+    if (m0 >= 2) w |= NW_OWN_RES | (m0 == 3 ? NW_OWN_ID : 0u);
     sfor<L::Q - 1>([&](auto I) {
         constexpr int i = decltype(I)::value + 1;
         const int aa = wrap_any(a - L::ea(i), NA);
         const int bb = wrap_any(b - L::eb(i), NB);
         const int cc = wrap_any(c - L::ec(i), NCc);
-        if (mask[(cc * NB + bb) * NA + aa]) w |= 1u << i;
+        const uint32_t ms = mask[(cc * NB + bb) * NA + aa];
+        if (ms) w |= 1u << i;
+        if (ms >= 2 && m0 == 0) w |= (L::ec(i) > 0 ? NW_RES_LO : NW_RES_HI) | (ms == 3 ? NW_RES_ID : 0u);
     });
     nbr[n] = w;
 }
 
 // Populations such that the first pull gives f = f^eq(rho0, u0) at every
 // fluid node: f*_i(y) = f^eq_i(y + e_i) when y + e_i is fluid, else the
-// population bounced back into y, f^eq_opp(i)(y).
+// population bounced back into y, f^eq_opp(i)(y), or, where y + e_i is a
+// reservoir, the value 2 w_o rho_res - f^eq_o(y) (o = opp(i)) that the
+// anti-bounce-back turns into f^eq_o(y).
+struct ResRho {
+    double r[2][2];
+};
 template <int LAT, int NC, int ST>
 __global__ void k_init(const typename Store<ST>::R* __restrict__ rho0,
                        const typename Store<ST>::R* __restrict__ u0, const uint32_t* __restrict__ nbr,
-                       void* fout, float* rout, int NA, int NB, int NCc) {
+                       void* fout, float* rout, int NA, int NB, int NCc, ResRho res) {
     using L = Lat<LAT>;
     using SS = Store<ST>;
     using S = typename SS::S;
@@ -1449,7 +1510,12 @@ __global__ void k_init(const typename Store<ST>::R* __restrict__ rho0,
             constexpr int o = opp(i);
             R v = 0;
             if (!(word & 1u)) {
-                if ((word >> o) & 1u && i != 0) {
+                // y + e_i lies in a reservoir plane
+                const bool to_res = (L::ec(i) < 0 && (word & NW_RES_LO)) || (L::ec(i) > 0 && (word & NW_RES_HI));
+                if (to_res) {
+                    const R rr = (R)res.r[(word & NW_RES_ID) ? 1 : 0][k];
+                    v = (R)(2.0 * L::w(o)) * rr - feq(k, n, o, L::ex[o], L::ey[o], L::ez[o], L::w(o));
+                } else if ((word >> o) & 1u && i != 0) {
                     v = feq(k, n, o, L::ex[o], L::ey[o], L::ez[o], L::w(o));
                 } else {
                     const int aa = wrap_any(a + L::ea(i), NA);

@@ -51,6 +51,12 @@ struct lbm_handle {
     bool have_prev;
     bool wet_uniform;  // no per-node wetting field was given: p.wet[k] everywhere
     bool mostly_fluid; // under 10 % solid nodes: tiles carry even work
+    bool has_res;      // the mask has reservoir nodes (open boundaries)
+    // reservoir densities of the streaming that the next pull completes: the
+    // pull of step t streams the populations of step t - 1, so a density set
+    // between steps reaches the anti-bounce-back inflow one step later
+    // (p.res_rho, the newest value, is what the force gather sees at once)
+    double res_active[2][2];
     int chunk_override;
 };
 

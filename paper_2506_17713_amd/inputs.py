@@ -257,6 +257,48 @@ def two_component_pack(n=400, steps=100, storage="F32", seed=0, porosity=0.35, r
     return wl, solid, rho
 
 
+def pcsw_pack(n=256, buffer=8, steps=1000, storage="F32", seed=3, porosity=0.381, radii=(8.0, 16.0),
+              rho_major=1.0, minor_frac=0.03, phi_w=1.2, drho_nw=0.1, dp_rho=0.0, shape=None,
+              collision="BGK"):
+    """Drainage for a capillary pressure - saturation curve (Sec. 3.4.3):
+    D3Q19 two-component Shan-Chen (psi = rho; g_kk = -0.027, g_12 = 0.57,
+    A = 0, both components of the same density) in a sphere pack of
+    porosity 0.381 along z, with buffers of `buffer` fluid planes at both
+    ends and a reservoir plane beyond each: reservoir 0 (z = 0, the inlet)
+    holds the non-wetting bulk composition with its major density raised
+    by dp_rho, reservoir 1 (the last plane, the outlet) the wetting bulk.
+    Solid walls close the x and y faces (one solid layer at x = 0 and at
+    y = 0, which the periodic wrap puts on both sides).  The pores and the
+    outlet buffer start filled with the wetting component 1, the inlet
+    buffer with the non-wetting component 0.  The measurement window is the
+    pack's planes.  Wetting as in two_component_pack (wetting phi_w,
+    non-wetting drho_nw).  Returns (workload, mask with values 0-3, rho)."""
+    if shape is None:
+        shape = (n + 2 * buffer + 2, n, n)
+    nz, ny, nx = shape
+    z0, z1 = 1 + buffer, nz - 1 - buffer  # the pack's planes [z0, z1)
+    pack = sphere_pack((z1 - z0, ny, nx), radii, porosity, seed)
+    mask = np.zeros(shape, np.uint8)
+    mask[z0:z1] = pack
+    mask[:, :, 0] = 1
+    mask[:, 0, :] = 1
+    mask[0] = 2
+    mask[nz - 1] = 3
+    minor = minor_frac * rho_major
+    nw = np.zeros(shape, bool)
+    nw[:z0] = True
+    rho = np.empty((2,) + tuple(shape))
+    rho[0] = np.where(nw, rho_major, minor)
+    rho[1] = np.where(nw, minor, rho_major)
+    g = ((-0.027, 0.57), (0.57, -0.027))
+    wl = Workload("pcsw_pack", "D3Q19", tuple(shape), nc=2, storage=storage, collision=collision,
+                  tau=(1.0, 1.0), psi_kind=("DENSITY", "DENSITY"), A=(0.0, 0.0), g=g,
+                  wet_mode=("DRHO", "PHI"), wet=(drho_nw, phi_w), rho_min=(0.0, 0.0),
+                  rho_max=(1.1 * rho_major, 1.1 * rho_major),
+                  res_rho=((rho_major + dp_rho, minor), (minor, rho_major)), window=(z0, z1), steps=steps)
+    return wl, mask, rho
+
+
 def adjoint_pack(n=128, steps=1000, storage="F32", seed=1, porosity=0.4, radii=(6.0, 14.0),
                  tr=0.8, phi=1.2, w=5.0, collision="MRT", shape=None, solid=None):
     """D3Q19 single-component CS at T_r = 0.8 in a periodic sphere pack; liquid

@@ -20,7 +20,7 @@ ERRORS = {-1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP", -4: "
           -5: "LBM_ERR_SPACE", -6: "LBM_ERR_OOM"}
 STORAGE = {"F64": 0, "F32": 1, "F16DEV": 2, "BF16DEV": 3, "F32F64": 4}
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_moments", "lbm_stats", "lbm_sync",
-           "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_reset", "lbm_grad_workspace_size", "lbm_grad",
+           "lbm_set_reservoir", "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_reset", "lbm_grad_workspace_size", "lbm_grad",
            "lbm_free", "lbm_strerror"]
 OBSERVABLES = {"saturation": 0, "drho": 1}
 
@@ -42,6 +42,7 @@ class LbmParams(C.Structure):
         ("eos_T", C.c_double * 2), ("alpha", C.c_double * 2), ("A", C.c_double * 2),
         ("g", (C.c_double * 2) * 2), ("body_accel", C.c_double * 3), ("wet", C.c_double * 2),
         ("rho_min", C.c_double * 2), ("rho_max", C.c_double * 2), ("kappa", C.c_double * 2),
+        ("res_rho", (C.c_double * 2) * 2), ("window", C.c_int32 * 2), ("reserved2", C.c_int32 * 2),
     ]
 
 
@@ -50,12 +51,16 @@ class LbmStats(C.Structure):
         ("step", C.c_int64), ("mass", C.c_double * 2), ("momentum", C.c_double * 3),
         ("residual", C.c_double), ("saturation", C.c_double), ("mean_ux", C.c_double),
         ("n_fluid", C.c_int64), ("nonfinite", C.c_int32), ("negative", C.c_int32),
+        ("p_nonwetting", C.c_double), ("p_wetting", C.c_double), ("capillary_pressure", C.c_double),
+        ("s_wetting", C.c_double),
     ]
 
     def as_dict(self) -> dict:
         return {"step": self.step, "mass": list(self.mass), "momentum": list(self.momentum),
                 "residual": self.residual, "saturation": self.saturation, "mean_ux": self.mean_ux,
-                "n_fluid": self.n_fluid, "nonfinite": self.nonfinite, "negative": self.negative}
+                "n_fluid": self.n_fluid, "nonfinite": self.nonfinite, "negative": self.negative,
+                "p_nonwetting": self.p_nonwetting, "p_wetting": self.p_wetting,
+                "capillary_pressure": self.capillary_pressure, "s_wetting": self.s_wetting}
 
 
 class LbmGradReq(C.Structure):
@@ -83,6 +88,7 @@ def load():
         lib.lbm_moments.argtypes = [vp, C.c_int, vp, vp]
         lib.lbm_stats.argtypes = [vp, vp]
         lib.lbm_sync.argtypes = [vp]
+        lib.lbm_set_reservoir.argtypes = [vp, C.c_int, vp]
         lib.lbm_state_bytes.argtypes = [vp, C.POINTER(sz)]
         lib.lbm_get_state.argtypes = [vp, vp]
         lib.lbm_set_state.argtypes = [vp, vp]
@@ -130,8 +136,11 @@ def params_from(w, check_every: int = 0) -> LbmParams:
         p.wet[k] = w.wet[k]
         p.rho_min[k], p.rho_max[k] = w.rho_min[k], min(w.rho_max[k], 1e300)
         p.kappa[k] = w.kappa[k]
+        for r in range(2):
+            p.res_rho[r][k] = w.res_rho[r][k]
     for d in range(3):
         p.body_accel[d] = w.body[d]
+    p.window[0], p.window[1] = w.window
     return p
 
 
@@ -197,6 +206,11 @@ class Solver:
 
     def sync(self) -> int:
         return self.lib.lbm_sync(self.h)
+
+    def set_reservoir(self, r: int, rho) -> None:
+        """New fixed densities (one per component) of reservoir r, from the next step on."""
+        buf = _host(list(rho)[: self.w.nc], np.float64)
+        _check("lbm_set_reservoir", self.lib.lbm_set_reservoir(self.h, int(r), buf.ctypes.data_as(C.c_void_p)))
 
     def state_bytes(self) -> int:
         b = C.c_size_t()

@@ -163,3 +163,33 @@ def test_surrogate_flop_count_matches_the_layer_shapes():
     f = bench.conv_flops(ARCH, 16)
     assert f["forward"] == fwd
     assert f["backward"] == 2 * fwd - first
+
+
+def test_init_rejects_bad_reservoir_masks(lib):
+    # reservoirs fill whole planes of the marching axis, one per plane, with
+    # positive densities; no fluid plane lies between two reservoir planes
+    w, mask, rho = inputs.pcsw_pack(n=12, buffer=2, shape=(18, 12, 12))
+    sz = C.c_size_t()
+    h = C.c_void_p()
+    fake_ws = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    r = np.ascontiguousarray(rho.reshape(2, -1))
+
+    def init(p, m):
+        m = np.ascontiguousarray(m.reshape(-1).astype(np.uint8))
+        assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == 0
+        return lib.lbm_init(C.byref(p), m.ctypes.data, r.ctypes.data, None, None, fake_ws, sz.value, None,
+                            C.byref(h))
+
+    p = lbm.params_from(w)
+    bad = []
+    m = mask.copy(); m[0, 3, 4] = 0; bad.append((p, m))            # a hole in the reservoir plane
+    m = mask.copy(); m[0, 3, 4] = 3; bad.append((p, m))            # two reservoirs in one plane
+    m = mask.copy(); m[5, 5, 5] = 4; bad.append((p, m))            # unknown node kind
+    m = mask.copy(); m[2] = 3; bad.append((p, m))                  # plane 1 between two reservoirs
+    q = lbm.params_from(w.with_(res_rho=((1.0, 0.0), (0.03, 1.0)))); bad.append((q, mask))  # rho_res = 0
+    for p_, m in bad:
+        assert init(p_, m) == -1
+    p = lbm.params_from(w)
+    p.reserved2[0] = 1
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -1
+    assert lib.lbm_set_reservoir(None, 0, None) == -1
