@@ -80,15 +80,21 @@ typedef struct {
     double res_rho[2][MAXC];           /* densities of reservoirs 0 and 1      */
 } oref_params;
 
-/* Node kinds of the mask: fluid, solid (bounce-back wall or grain), and two
- * reservoirs.  A reservoir node is an open boundary held at fixed component
- * densities res_rho[r][k] and at rest: it emits the rest equilibrium
- * f^eq(res_rho, 0) into its fluid neighbours, and enters their force gather
- * and the virtual densities of solids with psi(res_rho), like fluid.  It is
- * not itself updated. */
+/* Node kinds of the mask: fluid, solid (bounce-back wall or grain), two
+ * reservoirs and a convective outlet.  A reservoir node is an open boundary
+ * held at fixed component densities res_rho[r][k]: a population that streams
+ * in from it is 2 w_i res_rho - f*_opp(i)(x) (anti-bounce-back), and it enters
+ * its neighbours' force gather and the virtual densities of solids with
+ * psi(res_rho), like fluid.  A convective outlet node (one plane of the
+ * slowest axis, fluid on its lower side) passes the flow out: a population
+ * that streams in from it obeys the convective equation d f/dt + U d f/dn = 0
+ * with U the mean outward velocity of the plane below (Sec. 3.4.2), and its
+ * density is that of the fluid node below it (zero gradient).  Neither kind
+ * is itself updated. */
 #define NODE_FLUID 0
 #define NODE_SOLID 1
-#define IS_RES(v) ((v) >= 2)
+#define NODE_CONV 4
+#define IS_RES(v) ((v) == 2 || (v) == 3)
 
 /* ------------------------------------------------------------------------ */
 /* Lattice tables built from the definition of the velocity sets.           */
@@ -385,10 +391,22 @@ static void fields(const oref_params *p, const geom_t *G, const uint8_t *solid,
         }
     }
 
+    /* 1b. Convective outlet nodes: the density of the node below (zero
+     * gradient along the outward normal +c), res_rho[1] if that is not fluid. */
+    const long plane = p->lattice == 0 ? p->nx : (long)p->nx * p->ny;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        if (solid[n] != NODE_CONV) continue;
+        long m = n - plane;
+        if (m < 0) m += N;
+        for (int k = 0; k < nc; ++k)
+            W->rho[(long)k * N + n] = solid[m] == NODE_FLUID ? W->rho[(long)k * N + m] : p->res_rho[1][k];
+    }
+
     /* 2. Improved virtual density (Eq. 17) at solid nodes with a fluid
      * neighbour: weighted average of fluid-neighbour densities, scaled by
      * phi or shifted by -drho, then limited to [rho_min, rho_max].  A
-     * reservoir neighbour counts as fluid. */
+     * reservoir or outlet neighbour counts as fluid. */
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
         W->active[n] = 0;
@@ -645,6 +663,59 @@ static void stream(const oref_params *p, const geom_t *G, const uint8_t *solid,
             }
 }
 
+/* 7b. Convective outlet (Sec. 3.4.2): a population f_i that streams into the
+ * fluid node x from the outlet plane above it (e_i pointing down, -c) solves
+ * d f/dt + U d f/dc = 0 by the implicit upwind step
+ *   f_i(x, t+1) = (f_i(x, t) + U f_i(x - c, t+1)) / (1 + U),
+ * with U = max(0, mean over the fluid nodes of the plane below the outlet of
+ * the bare outward velocity sum_k j_c^k / sum_k rho^k at time t) -- the
+ * average-velocity form -- and f_i(x - c, t+1) the population just streamed
+ * into the node below x (f_i(x, t) again where that node is not fluid).
+ * fold holds f(t), f holds f(t+1) from the plain streaming. */
+static void convective_outlet(const oref_params *p, const geom_t *G, const uint8_t *solid,
+                              const work_t *W, const real_t *fold, real_t *f)
+{
+    const lattice_t *L = &G->L;
+    const long N = G->N;
+    const int q = L->q, nc = p->nc;
+    const long plane = p->lattice == 0 ? p->nx : (long)p->nx * p->ny;
+    const int cax = p->lattice == 0 ? 1 : 2; /* the slowest axis: y in 2-D, z in 3-D */
+    real_t usum = 0.0;
+    long cnt = 0;
+    for (long n = 0; n < N; ++n) {
+        if (solid[n] != NODE_FLUID) continue;
+        long up = n + plane;
+        if (up >= N) up -= N;
+        if (solid[up] != NODE_CONV) continue;
+        real_t jc = 0.0, r = 0.0;
+        for (int k = 0; k < nc; ++k) {
+            jc += W->j[((long)k * 3 + cax) * N + n];
+            r += W->rho[(long)k * N + n];
+        }
+        usum += jc / r;
+        ++cnt;
+    }
+    real_t U = cnt ? usum / (double)cnt : 0.0;
+    if (RE(U) < 0.0) U = 0.0;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        if (solid[n] != NODE_FLUID) continue;
+        long below = n - plane;
+        if (below < 0) below += N;
+        for (int i = 0; i < q; ++i) {
+            if (L->e[i][cax] != -1) continue;
+            int src = G->nbr[L->opp[i] * N + n]; /* n - e_i, in the plane above */
+            if (solid[src] != NODE_CONV) continue;
+            for (int k = 0; k < nc; ++k) {
+                long a = ((long)k * q + i) * N;
+                real_t prev = fold[a + n];
+                real_t upw = solid[below] == NODE_FLUID ? f[a + below] : prev;
+                f[a + n] = (prev + U * upw) / (1.0 + U);
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Exported API.                                                            */
 /* ------------------------------------------------------------------------ */
@@ -768,7 +839,7 @@ int API(step)(const oref_params *p, const uint8_t *solid, const real_t *wet, rea
     double M[MAXQ][MAXQ], Mi[MAXQ][MAXQ];
     if (p->nc < 1 || p->nc > MAXC) return -1;
     for (long n = 0; n < (long)p->nx * p->ny * p->nz; ++n)
-        if (solid[n] > 3) return -5;
+        if (solid[n] > 4) return -5;
     for (int k = 0; k < p->nc; ++k)
         if (p->kappa[k] != 0.0 && (p->lattice != 0 || p->collision != 1)) return -4;
     if (p->collision == 2 && p->nc != 1) return -4;
@@ -781,11 +852,22 @@ int API(step)(const oref_params *p, const uint8_t *solid, const real_t *wet, rea
     if (work_alloc(p, G.N, &W)) return -2;
     real_t *fpost = (real_t *)malloc(sizeof(real_t) * p->nc * G.L.q * G.N);
     if (!fpost) return -2;
+    int has_conv = 0;
+    for (long n = 0; n < G.N; ++n) has_conv |= solid[n] == NODE_CONV;
+    real_t *fold = has_conv ? (real_t *)malloc(sizeof(real_t) * p->nc * G.L.q * G.N) : NULL;
+    if (has_conv && !fold) return -2;
     for (int s = 0; s < nsteps; ++s) {
         fields(p, &G, solid, wet, f, &W);
         collide(p, &G, solid, f, &W, M, Mi, fpost);
-        stream(p, &G, solid, fpost, f);
+        if (has_conv) {
+            memcpy(fold, f, sizeof(real_t) * p->nc * G.L.q * G.N);
+            stream(p, &G, solid, fpost, f);
+            convective_outlet(p, &G, solid, &W, fold, f);
+        } else {
+            stream(p, &G, solid, fpost, f);
+        }
     }
+    free(fold);
     free(fpost);
     work_free(&W);
     geom_free(&G);

@@ -11,7 +11,13 @@ Poiseuille flow of the pressure gradient they set up, with that gradient
 reaching the imposed densities at the halfway planes; the mixture pressure
 is alpha p_EOS for one component and equal in the two bulks of a flat
 two-component interface; the capillary measurement of a state with known
-phases gives its volume fraction and pressure difference."""
+phases gives its volume fraction and pressure difference.
+
+The convective outlet (mask 4, Sec. 3.4.2) keeps a fluid at rest exactly
+and passes a developed channel flow unchanged, where a closed end stops it.
+Its rate term (the mean outward velocity U) acts only in transients, which
+these pins do not separate from the U = 0 limit: that part is checked
+against the GPU path but not pinned on its own."""
 import numpy as np
 import pytest
 
@@ -179,3 +185,54 @@ def test_one_component_capillary_classes_vapour_as_non_wetting(oracle_mod):
     pv = eos.CS.pressure(e["rho_v"], e["T"])
     pl = eos.CS.pressure(e["rho_l"], e["T"])
     assert cap["p_c"] == pytest.approx(pv - pl, rel=1e-10, abs=1e-14)
+
+
+# ------------------------------------------------------ convective outlet
+def _developed_channel(oracle_mod, nx=22, ny=40, tau=0.8, g=1e-5):
+    """Body-force channel flow along y between the halfway walls of column
+    x = 0, run to its periodic steady state from the plane Poiseuille profile."""
+    wall = np.zeros((1, ny, nx), np.uint8)
+    wall[0, :, 0] = 1
+    w = Workload("conv", "D2Q9", (1, ny, nx), tau=(tau, tau), body=(0.0, g, 0.0),
+                 res_rho=((1.0, 1.0), (1.0, 1.0)), **IDEAL)
+    nu, H = (tau - 0.5) / 3.0, nx - 1
+    xs = np.arange(nx) - 0.5 * nx
+    prof = np.where(np.arange(nx) > 0, g / (2.0 * nu) * (H * H / 4.0 - xs ** 2), 0.0)
+    u0 = np.zeros((3, 1, ny, nx))
+    u0[1] = prof
+    per = oracle_mod.State(w, wall, np.ones((1, 1, ny, nx)), u0=u0)
+    per.step(4000)
+    return w, wall, per, prof
+
+
+def test_convective_outlet_keeps_a_fluid_at_rest(oracle_mod):
+    nx, ny = 12, 20
+    mask = channel_2d(nx, ny, res=(2, 4))
+    w = Workload("rest", "D2Q9", (1, ny, nx), tau=(0.8, 0.8), res_rho=((1.0, 1.0), (1.0, 1.0)), **IDEAL)
+    st = oracle_mod.State(w, mask, np.ones((1, 1, ny, nx)))
+    f0 = st.f.copy()
+    st.step(300)
+    assert np.abs(st.f - f0).max() < 1e-14
+
+
+def test_convective_outlet_passes_a_developed_flow(oracle_mod):
+    # the periodic channel's steady flow, with its ends replaced by an inlet
+    # reservoir and an outlet: the convective outlet (zero normal gradient
+    # of a steady profile) passes it unchanged; a closed end stops it
+    w, wall, per, prof = _developed_channel(oracle_mod)
+    _, ny, nx = w.shape
+    u_per = per.fields()["umix"][1].reshape(ny, nx)
+    assert np.abs(u_per[ny // 2, 1:] - prof[1:]).max() < 3e-3 * prof.max()
+    dev = {}
+    for top in (4, 1):
+        mask = wall.copy()
+        mask[0, 0, :] = 2
+        mask[0, ny - 1, :] = top
+        st = oracle_mod.State(w, mask, np.ones((1, 1, ny, nx)))
+        st.f[:] = per.f
+        st.f[:, :, mask.reshape(-1) != 0] = 0.0
+        st.step(3000)
+        uy = st.fields()["umix"][1].reshape(ny, nx)
+        dev[top] = max(np.abs(uy[y, 1:] - u_per[y, 1:]).max() for y in (ny // 2, ny - 2)) / prof.max()
+    assert dev[4] < 5e-3
+    assert dev[1] > 0.5
