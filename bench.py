@@ -39,10 +39,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=None, help="lattice size (default: 256, 128 for droplet2d, "
                                                          "400 for pack2)")
-    ap.add_argument("--workload", default="sessile", choices=["sessile", "droplet2d", "pack2", "adjoint", "surrogate"],
+    ap.add_argument("--workload", default="sessile",
+                    choices=["sessile", "droplet2d", "pack2", "pcsw", "adjoint", "surrogate"],
                     help="sessile: D3Q19 MRT sessile droplet (the headline line); droplet2d: D2Q9 BGK FP64 "
-                         "droplet; pack2: D3Q19 two-component sphere pack; adjoint: gradient of the "
-                         "saturation over 1000 steps of the 128^3 pack (checkpoint every 100)")
+                         "droplet; pack2: D3Q19 two-component sphere pack; pcsw: two-component drainage of "
+                         "an n^3 pack between reservoirs (open boundaries, in-situ capillary pressure); "
+                         "adjoint: gradient of the saturation over 1000 steps of the 128^3 pack (checkpoint "
+                         "every 100)")
     ap.add_argument("--storage", default="F32", choices=["F32", "F64", "F32F64", "F16DEV", "BF16DEV"])
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -152,6 +155,10 @@ def make_workload(name: str, n: int, storage: str, collision: str):
         w, solid, rho = inputs.sessile_3d(n=n, r=float(r), storage=storage, collision=collision,
                                           wet_mode="PHI", wet=1.1)
         desc = f"sessile droplet D3Q19 {collision} Shan-Chen CS T=0.8Tc {n}^3 r={r} wall z=0 phi=1.1"
+    elif name == "pcsw":
+        w, solid, rho = inputs.pcsw_pack(n=n, buffer=8, storage=storage, dp_rho=0.05)
+        desc = (f"capillary pressure - saturation drainage, two-component Shan-Chen D3Q19 BGK, {n}^3 sphere pack "
+                f"porosity 0.381 radii 8-16, 8-plane buffers, reservoir planes (inlet +0.05), walls on x/y")
     elif name == "droplet2d":
         w, solid, rho = inputs.droplet_2d(n=n, storage=storage, collision=collision)
         desc = f"droplet D2Q9 {collision} Shan-Chen CS T=0.7Tc {n}^2 r=20 periodic"
@@ -181,7 +188,7 @@ def cpu_baseline(budget_s: float, name: str) -> dict:
     thread for a quarter of the budget."""
     from oracle import oracle
 
-    n = {"sessile": 64, "droplet2d": 128, "pack2": 48}[name]
+    n = {"sessile": 64, "droplet2d": 128, "pack2": 48, "pcsw": 48}[name]
     w, solid, rho, desc = make_workload(name, n, "F64", "BGK" if name == "droplet2d" else "MRT")
     if name == "pack2":
         w = w.with_(collision="BGK")
@@ -353,7 +360,7 @@ def main():
     if args.workload == "surrogate":
         print(json.dumps(run_surrogate(args)), flush=True)
         return
-    n = args.n or {"sessile": 256, "droplet2d": 128, "pack2": 400}[args.workload]
+    n = args.n or {"sessile": 256, "droplet2d": 128, "pack2": 400, "pcsw": 256}[args.workload]
     storage = args.storage if args.workload != "droplet2d" or args.storage != "F32" else "F64"
     collision = "BGK" if args.workload != "sessile" else args.collision
     w, solid, rho, desc = make_workload(args.workload, n, storage, collision)

@@ -153,7 +153,7 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
  * pore-filling runs of Sec. 3).
  *   p          parameters, copied.
  *   mask       host uint8[N]: 0 = fluid, 1 = solid (walls, grains; halfway
- *              bounce-back), 2 / 3 = reservoir 0 / 1.  A reservoir is an open
+ *              bounce-back), 2 / 3 = reservoir 0 / 1, 4 = convective outlet.  A reservoir is an open
  *              boundary (Sec. 3.4.3: constant-pressure inlet and outlet) held
  *              at the densities p->res_rho[r] and at rest: a population that
  *              would stream in from it is 2 w_i rho_res - f*_opp(i)(x) (anti-
@@ -163,6 +163,14 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
  *              whole planes of the slowest axis (z; y in 2-D), one reservoir
  *              per plane, and no fluid node may touch reservoir planes on
  *              both sides (LBM_ERR_ARG otherwise).
+ *              A convective outlet (Sec. 3.4.2) is one whole plane with fluid
+ *              in the plane below it and none above: a population that
+ *              streams down into the fluid from it follows the convective
+ *              equation d f/dt + U d f/dc = 0, (f(t) + U f_below(t+1)) /
+ *              (1 + U), with U = max(0, mean j_c / rho) over the fluid of the
+ *              plane below at time t; its density in the force gather is
+ *              that of the node below it (res_rho[1] where that is solid).
+ *              Not with 16-bit storage (LBM_ERR_UNSUPPORTED).
  *   rho0       host double[n_comp][N], initial density per component.
  *   u0         host double[3][N] initial equilibrium velocity j/rho (x, y, z),
  *              or NULL for rest.  The velocity of Eq. 6 reported by

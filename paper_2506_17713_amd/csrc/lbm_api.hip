@@ -110,6 +110,9 @@ Layout layout_of(const lbm_params* p) {
     L.uxprev = take(N * rb);
     L.partial = take((size_t)kRedBlocks * kStatSlots * 8);
     L.dstats = take(kStatSlots * 8 + 8);
+    // convective outlet: partial sums of the mean outward velocity
+    const size_t plane = (size_t)p->nx * (p->lattice == LBM_D2Q9 ? 1 : p->ny);
+    L.conv_part = take(((plane + kConvThreads - 1) / kConvThreads) * 16);
     L.total = off;
     return L;
 }
@@ -232,6 +235,9 @@ hipError_t launch_step(lbm_handle* h, StepArgs<typename Store<ST>::R>& a) {
         const int minc = LAT == LAT_D2Q9 ? 4 : 16;
         if (chunk < minc) chunk = minc;
     }
+    // an outlet plane (the last one) must not open a chunk's ring: its
+    // density is copied from the ring's plane below it
+    if (h->conv_plane >= 0 && chunk < 2) chunk = 2;
     if (chunk > h->NCc) chunk = h->NCc;
     a.chunk = chunk;
     const int nchunks = (h->NCc + chunk - 1) / chunk;
@@ -295,6 +301,41 @@ hipError_t dispatch_store(lbm_handle* h, bool mom, int comp, void* rho, void* u,
             return dispatch_coll<LAT, NC, ST_BF16>(h, mom, a);
         }
     }
+}
+
+// Convective outlet after a step, on the handle's buffers before the swap:
+// the mean outward velocity of the plane below the outlet, then the
+// populations that stream in from the outlet at the next pull.
+template <int LAT, int NC, int ST>
+hipError_t conv_launch(lbm_handle* h) {
+    using R = typename Store<ST>::R;
+    StepArgs<R> a;
+    fill_args(h, a, nullptr);
+    const int plane = h->NA * h->NB;
+    const int nblk = (plane + kConvThreads - 1) / kConvThreads;
+    const int co = h->conv_plane, ci = (co + h->NCc - 1) % h->NCc;
+    double* part = reinterpret_cast<double*>(h->ws + h->lay.conv_part);
+    hipLaunchKernelGGL((k_conv_u<LAT, NC, ST>), dim3(nblk), dim3(kConvThreads), 0, h->stream, a, ci, part);
+    hipLaunchKernelGGL((k_conv_ghost<LAT, NC, ST>), dim3(nblk), dim3(kConvThreads), 0, h->stream, a, co,
+                       (const double*)part, nblk);
+    return hipGetLastError();
+}
+
+template <int LAT, int NC>
+hipError_t conv_store(lbm_handle* h) {
+    switch (h->p.storage) {
+        case LBM_STORE_F64: return conv_launch<LAT, NC, ST_F64>(h);
+        case LBM_STORE_F32: return conv_launch<LAT, NC, ST_F32>(h);
+        case LBM_STORE_F32_F64: return conv_launch<LAT, NC, ST_F32D>(h);
+        default: return hipErrorInvalidValue;  // rejected at lbm_init
+    }
+}
+
+hipError_t run_conv(lbm_handle* h) {
+    if (h->conv_plane < 0) return hipSuccess;
+    if (h->p.lattice == LBM_D2Q9)
+        return h->p.n_comp == 1 ? conv_store<LAT_D2Q9, 1>(h) : conv_store<LAT_D2Q9, 2>(h);
+    return h->p.n_comp == 1 ? conv_store<LAT_D3Q19, 1>(h) : conv_store<LAT_D3Q19, 2>(h);
 }
 
 hipError_t run_kernel(lbm_handle* h, bool mom, int comp = -1, void* rho = nullptr, void* u = nullptr,
@@ -518,14 +559,15 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     // lies between two reservoir planes
     const size_t plane = (size_t)p->nx * (p->lattice == LBM_D2Q9 ? 1 : p->ny);
     const size_t n_planes = N / plane;
-    std::vector<int> kind(n_planes, 0);  // 0 none, 1 fluid, 2 / 3 reservoir
+    std::vector<int> kind(n_planes, 0);  // 0 none, 1 fluid, 2 / 3 reservoir, 4 outlet
     bool has_res = false;
+    int conv_plane = -1;
     for (size_t c = 0; c < n_planes; ++c) {
         const uint8_t* m = mask + c * plane;
         const uint8_t m0 = m[0];
         size_t nres = 0, nfl = 0;
         for (size_t i = 0; i < plane; ++i) {
-            if (m[i] > 3) return LBM_ERR_ARG;
+            if (m[i] > 4) return LBM_ERR_ARG;
             if (m[i] >= 2) {
                 if (m[i] != m0) return LBM_ERR_ARG;
                 ++nres;
@@ -536,13 +578,25 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
         kind[c] = nres ? m0 : (nfl ? 1 : 0);
         if (nres) {
             has_res = true;
+            const int r = m0 == 4 ? 1 : m0 - 2;  // the outlet's fallback density is reservoir 1's
             for (int k = 0; k < nc; ++k)
-                if (!std::isfinite(p->res_rho[m0 - 2][k]) || !(p->res_rho[m0 - 2][k] > 0.0)) return LBM_ERR_ARG;
+                if (!std::isfinite(p->res_rho[r][k]) || !(p->res_rho[r][k] > 0.0)) return LBM_ERR_ARG;
+        }
+        if (m0 == 4 && nres) {
+            if (conv_plane >= 0) return LBM_ERR_ARG;  // one outlet plane
+            conv_plane = (int)c;
         }
     }
     for (size_t c = 0; c < n_planes && has_res; ++c)
         if (kind[c] == 1 && kind[(c + n_planes - 1) % n_planes] >= 2 && kind[(c + 1) % n_planes] >= 2)
             return LBM_ERR_ARG;
+    if (conv_plane >= 0) {
+        // the last plane of the marching axis, fluid below it and none in
+        // the first plane (above it across the wrap); full-precision storage
+        if (n_planes < 4 || conv_plane != (int)n_planes - 1 || kind[n_planes - 2] != 1 || kind[0] == 1)
+            return LBM_ERR_ARG;
+        if (is_dev(p->storage)) return LBM_ERR_UNSUPPORTED;
+    }
     size_t n_solid = 0;
     for (size_t n = 0; n < N; ++n) {
         if (mask[n]) {
@@ -573,6 +627,7 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     h->have_prev = false;
     h->wet_uniform = wet == nullptr;
     h->has_res = has_res;
+    h->conv_plane = conv_plane;
     std::memcpy(h->res_active, p->res_rho, sizeof(h->res_active));
     h->mostly_fluid = n_solid * 10 < N;
     // LBM_CHUNK (environment, tuning only): planes per workgroup along the
@@ -645,6 +700,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps) {
     if (!h || nsteps < 0) return LBM_ERR_ARG;
     for (int64_t s = 0; s < nsteps; ++s) {
         if (run_kernel(h, false) != hipSuccess) return LBM_ERR_HIP;
+        if (run_conv(h) != hipSuccess) return LBM_ERR_HIP;
         std::memcpy(h->res_active, h->p.res_rho, sizeof(h->res_active));
         h->cur ^= 1;
         h->step += 1;

@@ -362,6 +362,7 @@ constexpr uint32_t NW_RES_HI = 1u << 21;   // plane c + 1 is a reservoir
 constexpr uint32_t NW_RES_ID = 1u << 22;   // ... and it is reservoir 1
 constexpr uint32_t NW_OWN_RES = 1u << 23;  // the node is a reservoir node
 constexpr uint32_t NW_OWN_ID = 1u << 24;   // ... of reservoir 1
+constexpr uint32_t NW_OWN_CONV = 1u << 25; // the node is in the convective outlet plane
 
 __device__ __forceinline__ int wrap_near(int v, int n) {
     // v in [-n, 2n)
@@ -555,8 +556,12 @@ __device__ __forceinline__ void open_fix(const StepArgs<R>& P, uint32_t word, R 
 // Density a non-fluid node shows its neighbours in the rho ring: a
 // reservoir's fixed density, else the solid marks (-1: its virtual density is
 // needed, -2: no fluid neighbour).
+// A convective outlet node (the last plane of the marching axis) takes the
+// density of the node below it, which the ring holds one slot back (`below`;
+// a solid mark there gives reservoir 1's density).
 template <class R>
-__device__ __forceinline__ R nonfluid_rho(const StepArgs<R>& P, uint32_t word, int k, R mark) {
+__device__ __forceinline__ R nonfluid_rho(const StepArgs<R>& P, uint32_t word, int k, R mark, R below) {
+    if (word & NW_OWN_CONV) return below >= (R)0 ? below : P.res_rho[1][k];
     return (word & NW_OWN_RES) ? P.res_rho[(word & NW_OWN_ID) ? 1 : 0][k] : mark;
 }
 
@@ -775,6 +780,7 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
 
     auto fill_rho = [&](int cp, R(&fo)[NC][Q]) {
         const int slot = (cp - c0 + 5) % 5;
+        const int bslot = (cp - c0 + 4) % 5;  // plane cp - 1 (an outlet plane is never the first of the ring)
         const int c = wrap_c(cp);
         const uint32_t wo = w_own;
         s_word[(cp - c0 + 3) % 3][tid] = wo;  // read back by this thread at the plane's collision
@@ -818,7 +824,8 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
             if (!(wo & 1u)) rs_scale(fo, wo, (lb_own + 3) * SWA + la_own + 3, cp);
         if (wo & 1u) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) s_rho[slot][k][own_idx] = nonfluid_rho(P, wo, k, solid_mark(wo));
+            for (int k = 0; k < NC; ++k)
+                s_rho[slot][k][own_idx] = nonfluid_rho(P, wo, k, solid_mark(wo), s_rho[bslot][k][own_idx]);
         } else {
             open_fix<LAT, NC>(P, wo, fo);
 #pragma unroll
@@ -829,7 +836,8 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
             if (!h_on[j]) continue;
             if (wh[j] & 1u) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = nonfluid_rho(P, wh[j], k, solid_mark(wh[j]));
+                for (int k = 0; k < NC; ++k)
+                    s_rho[slot][k][h_idx[j]] = nonfluid_rho(P, wh[j], k, solid_mark(wh[j]), s_rho[bslot][k][h_idx[j]]);
             } else if (!need(j)) {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) s_rho[slot][k][h_idx[j]] = (R)0;  // never read
@@ -1447,9 +1455,10 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
 // ---------------------------------------------------------------------------
 // Initialisation kernels.
 // ---------------------------------------------------------------------------
-// Neighbour words from the mask (0 fluid, 1 solid, 2 / 3 reservoir 0 / 1):
-// bit 0 = the node is not fluid, bit i = the node n - e_i is not fluid, and
-// the reservoir bits NW_*.
+// Neighbour words from the mask (0 fluid, 1 solid, 2 / 3 reservoir 0 / 1,
+// 4 convective outlet): bit 0 = the node is not fluid, bit i = the node
+// n - e_i is solid or a reservoir (the pull takes the node's own opposite
+// population; an outlet node is pulled from like fluid), and the bits NW_*.
 template <int LAT>
 __global__ void k_nbr_words(const uint8_t* __restrict__ mask, uint32_t* __restrict__ nbr, int NA,
                             int NB, int NCc) {
@@ -1460,15 +1469,16 @@ __global__ void k_nbr_words(const uint8_t* __restrict__ mask, uint32_t* __restri
     const int a = n % NA, b = (n / NA) % NB, c = n / (NA * NB);
     const uint32_t m0 = mask[n];
     uint32_t w = m0 ? 1u : 0u;
-    if (m0 >= 2) w |= NW_OWN_RES | (m0 == 3 ? NW_OWN_ID : 0u);
+    if (m0 == 2 || m0 == 3) w |= NW_OWN_RES | (m0 == 3 ? NW_OWN_ID : 0u);
+    if (m0 == 4) w |= NW_OWN_CONV;
     sfor<L::Q - 1>([&](auto I) {
         constexpr int i = decltype(I)::value + 1;
         const int aa = wrap_any(a - L::ea(i), NA);
         const int bb = wrap_any(b - L::eb(i), NB);
         const int cc = wrap_any(c - L::ec(i), NCc);
         const uint32_t ms = mask[(cc * NB + bb) * NA + aa];
-        if (ms) w |= 1u << i;
-        if (ms >= 2 && m0 == 0) w |= (L::ec(i) > 0 ? NW_RES_LO : NW_RES_HI) | (ms == 3 ? NW_RES_ID : 0u);
+        if (ms && ms != 4) w |= 1u << i;
+        if ((ms == 2 || ms == 3) && m0 == 0) w |= (L::ec(i) > 0 ? NW_RES_LO : NW_RES_HI) | (ms == 3 ? NW_RES_ID : 0u);
     });
     nbr[n] = w;
 }
@@ -1509,7 +1519,13 @@ __global__ void k_init(const typename Store<ST>::R* __restrict__ rho0,
             constexpr int i = decltype(I)::value;
             constexpr int o = opp(i);
             R v = 0;
-            if (!(word & 1u)) {
+            if (word & NW_OWN_CONV) {
+                // an outlet node holds what streams into y + e_i from it
+                const int aa = wrap_any(a + L::ea(i), NA);
+                const int bb = wrap_any(b + L::eb(i), NB);
+                const int cc = wrap_any(c + L::ec(i), NCc);
+                v = feq(k, (cc * NB + bb) * NA + aa, i, L::ex[i], L::ey[i], L::ez[i], L::w(i));
+            } else if (!(word & 1u)) {
                 // y + e_i lies in a reservoir plane
                 const bool to_res = (L::ec(i) < 0 && (word & NW_RES_LO)) || (L::ec(i) > 0 && (word & NW_RES_HI));
                 if (to_res) {
@@ -1533,6 +1549,114 @@ __global__ void k_init(const typename Store<ST>::R* __restrict__ rho0,
             }
         });
     }
+}
+
+// ---------------------------------------------------------------------------
+// Convective outlet (Sec. 3.4.2): after a step that read fin and wrote fout,
+// the outlet plane c_o (fluid in the plane c_i = c_o - 1 below it) gets the
+// populations that stream into the fluid below at the next pull:
+//   g_i = (f_i(x, t) + U f_i(x - c, t + 1)) / (1 + U)     (e_c(i) = -1),
+// x = the node below the outlet node, f_i(x, t) = the value this step pulled
+// (fin at the outlet node), f_i(x - c, t + 1) = the population streaming into
+// the node below x (fout), U = max(0, mean j_c / rho over the fluid of c_i at
+// time t).  (The outlet's density, that of the node below it, is filled in
+// the rho ring.)  Storage F64 / F32 / F32-with-FP64 arithmetic.
+// ---------------------------------------------------------------------------
+constexpr int kConvThreads = 256;
+
+// Partial sums (sum u_c, count) of the fluid nodes of plane ci at time t.
+template <int LAT, int NC, int ST>
+__global__ void __launch_bounds__(kConvThreads)
+    k_conv_u(StepArgs<typename Store<ST>::R> P, int ci, double* __restrict__ part) {
+    using L = Lat<LAT>;
+    using R = typename Store<ST>::R;
+    const int plane = P.NA * P.NB;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double u = 0.0, cnt = 0.0;
+    if (t < plane) {
+        const int a = t % P.NA, b = t / P.NA;
+        const uint32_t word = P.nbr[(size_t)ci * plane + t];
+        if (!(word & 1u)) {
+            R f[NC][L::Q];
+            pull_node<LAT, ST, NC>(P, a, b, ci, word, f);
+            open_fix<LAT, NC>(P, word, f);
+            double jc = 0.0, r = 0.0;
+            for (int k = 0; k < NC; ++k)
+                for (int i = 0; i < L::Q; ++i) {
+                    r += (double)f[k][i];
+                    jc += (double)f[k][i] * L::ec(i);
+                }
+            u = jc / r;
+            cnt = 1.0;
+        }
+    }
+    __shared__ double sh[2][kConvThreads / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        u += __shfl_xor(u, o, 64);
+        cnt += __shfl_xor(cnt, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = u;
+        sh[1][threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double su = 0.0, sc = 0.0;
+        for (int w = 0; w < kConvThreads / 64; ++w) {
+            su += sh[0][w];
+            sc += sh[1][w];
+        }
+        part[2 * blockIdx.x] = su;
+        part[2 * blockIdx.x + 1] = sc;
+    }
+}
+
+// Ghost populations of the outlet plane co (one thread per outlet node).
+template <int LAT, int NC, int ST>
+__global__ void __launch_bounds__(kConvThreads)
+    k_conv_ghost(StepArgs<typename Store<ST>::R> P, int co, const double* __restrict__ part, int nblk) {
+    using L = Lat<LAT>;
+    using S = typename Store<ST>::S;
+    using R = typename Store<ST>::R;
+    constexpr int Q = L::Q;
+    const int NA = P.NA, NB = P.NB, NCc = P.NC_;
+    const int plane = NA * NB;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= plane) return;
+    double su = 0.0, sc = 0.0;  // same order in every thread: one U for the plane
+    for (int j = 0; j < nblk; ++j) {
+        su += part[2 * j];
+        sc += part[2 * j + 1];
+    }
+    double U = sc > 0.0 ? su / sc : 0.0;
+    U = U > 0.0 ? U : 0.0;
+    const int a = t % NA, b = t / NA;
+    const size_t N = (size_t)P.N;
+    const S* fin = reinterpret_cast<const S*>(P.fin);
+    S* fout = reinterpret_cast<S*>(P.fout);
+    const int ci = wrap_any(co - 1, NCc), cu = wrap_any(co - 2, NCc);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (L::ec(i) == -1) {
+            // x = the fluid node this population streams into; xu = the node below x
+            const int ax = wrap_any(a + L::ea(i), NA), bx = wrap_any(b + L::eb(i), NB);
+            const size_t nx_ = (size_t)ci * plane + bx * NA + ax;
+            const size_t nu = (size_t)cu * plane + bx * NA + ax;
+            const size_t no = (size_t)co * plane + t;
+            if (P.nbr[nx_] & 1u) return;
+            const uint32_t wu = P.nbr[nu];
+            // f_i(x - c, t + 1): from xu - e_i = the node below this outlet node, or bounced back
+            const size_t src = (size_t)ci * plane + t;
+            for (int k = 0; k < NC; ++k) {
+                const R prev = (R)fin[(size_t)(k * Q + i) * N + no];
+                R upw = prev;
+                if (!(wu & 1u)) upw = (wu >> i) & 1u ? (R)fout[(size_t)(k * Q + opp(i)) * N + nu]
+                                                     : (R)fout[(size_t)(k * Q + i) * N + src];
+                fout[(size_t)(k * Q + i) * N + no] = (S)((prev + (R)U * upw) / ((R)1 + (R)U));
+            }
+        }
+    });
 }
 
 }  // namespace lbm

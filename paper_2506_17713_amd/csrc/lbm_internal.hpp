@@ -18,7 +18,7 @@ constexpr int kRedThreads = 256;
 constexpr int kStatSlots = 16;    // doubles per partial / in the result
 
 struct Layout {
-    size_t fA, fB, rA, rB, nbr, wet, mrho, mu, uxprev, partial, dstats, total;
+    size_t fA, fB, rA, rB, nbr, wet, mrho, mu, uxprev, partial, dstats, conv_part, total;
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -57,6 +57,7 @@ struct lbm_handle {
     // between steps reaches the anti-bounce-back inflow one step later
     // (p.res_rho, the newest value, is what the force gather sees at once)
     double res_active[2][2];
+    int conv_plane;    // plane of the convective outlet, -1: none
     int chunk_override;
 };
 

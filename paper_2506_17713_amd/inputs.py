@@ -259,7 +259,7 @@ def two_component_pack(n=400, steps=100, storage="F32", seed=0, porosity=0.35, r
 
 def pcsw_pack(n=256, buffer=8, steps=1000, storage="F32", seed=3, porosity=0.381, radii=(8.0, 16.0),
               rho_major=1.0, minor_frac=0.03, phi_w=1.2, drho_nw=0.1, dp_rho=0.0, shape=None,
-              collision="BGK"):
+              collision="BGK", outlet="reservoir", body=0.0):
     """Drainage for a capillary pressure - saturation curve (Sec. 3.4.3):
     D3Q19 two-component Shan-Chen (psi = rho; g_kk = -0.027, g_12 = 0.57,
     A = 0, both components of the same density) in a sphere pack of
@@ -272,7 +272,10 @@ def pcsw_pack(n=256, buffer=8, steps=1000, storage="F32", seed=3, porosity=0.381
     outlet buffer start filled with the wetting component 1, the inlet
     buffer with the non-wetting component 0.  The measurement window is the
     pack's planes.  Wetting as in two_component_pack (wetting phi_w,
-    non-wetting drho_nw).  Returns (workload, mask with values 0-3, rho)."""
+    non-wetting drho_nw).  outlet="convective" puts a convective outlet
+    plane (mask 4) in place of reservoir 1, and body > 0 adds a body
+    acceleration along +z: the body-force drainage of Sec. 3.4.2.  Returns
+    (workload, mask with values 0-4, rho)."""
     if shape is None:
         shape = (n + 2 * buffer + 2, n, n)
     nz, ny, nx = shape
@@ -283,7 +286,7 @@ def pcsw_pack(n=256, buffer=8, steps=1000, storage="F32", seed=3, porosity=0.381
     mask[:, :, 0] = 1
     mask[:, 0, :] = 1
     mask[0] = 2
-    mask[nz - 1] = 3
+    mask[nz - 1] = 4 if outlet == "convective" else 3
     minor = minor_frac * rho_major
     nw = np.zeros(shape, bool)
     nw[:z0] = True
@@ -295,7 +298,8 @@ def pcsw_pack(n=256, buffer=8, steps=1000, storage="F32", seed=3, porosity=0.381
                   tau=(1.0, 1.0), psi_kind=("DENSITY", "DENSITY"), A=(0.0, 0.0), g=g,
                   wet_mode=("DRHO", "PHI"), wet=(drho_nw, phi_w), rho_min=(0.0, 0.0),
                   rho_max=(1.1 * rho_major, 1.1 * rho_major),
-                  res_rho=((rho_major + dp_rho, minor), (minor, rho_major)), window=(z0, z1), steps=steps)
+                  res_rho=((rho_major + dp_rho, minor), (minor, rho_major)), window=(z0, z1), steps=steps,
+                  body=(0.0, 0.0, body))
     return wl, mask, rho
 
 

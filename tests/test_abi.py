@@ -193,3 +193,28 @@ def test_init_rejects_bad_reservoir_masks(lib):
     p.reserved2[0] = 1
     assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -1
     assert lib.lbm_set_reservoir(None, 0, None) == -1
+
+
+def test_init_rejects_bad_convective_outlets(lib):
+    # one outlet plane, the last of the marching axis, with fluid below it
+    # and none above across the wrap; not with 16-bit storage
+    w, mask, rho = inputs.pcsw_pack(n=12, buffer=2, shape=(18, 12, 12), outlet="convective")
+    sz = C.c_size_t()
+    h = C.c_void_p()
+    fake_ws = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    r = np.ascontiguousarray(rho.reshape(2, -1))
+
+    def init(p, m):
+        m = np.ascontiguousarray(m.reshape(-1).astype(np.uint8))
+        assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == 0
+        return lib.lbm_init(C.byref(p), m.ctypes.data, r.ctypes.data, None, None, fake_ws, sz.value, None,
+                            C.byref(h))
+
+    p = lbm.params_from(w)
+    m = mask.copy(); m[0] = 4                       # two outlet planes
+    assert init(p, m) == -1
+    m = np.roll(mask, -1, axis=0)                   # outlet not the last plane
+    assert init(p, m) == -1
+    m = mask.copy(); m[0] = 0                       # fluid above the outlet across the wrap
+    assert init(p, m) == -1
+    assert init(lbm.params_from(w.with_(storage="F16DEV")), mask) == -2

@@ -145,3 +145,40 @@ def test_drainage_pack_16bit_reported(oracle_mod, storage):
     for c, (er, eu) in out.items():
         assert er < 5e-2 and eu < 0.5, (c, er, eu)
     assert st["nonfinite"] == 0 and st["negative"] == 0
+
+
+# ------------------------------------------------------ convective outlet
+@pytest.mark.parametrize("storage", ["F64", "F32"])
+@pytest.mark.parametrize("collision", ["BGK", "MRT"])
+def test_convective_outlet_channel_2d(oracle_mod, storage, collision):
+    # body-force channel between an inlet reservoir (row 0) and a convective
+    # outlet (the last row), started from the plane Poiseuille profile so
+    # that the mean outward velocity U is well above zero from the start
+    nx, ny, tau, g = 90, 61, 0.8, 2e-6
+    mask = np.zeros((1, ny, nx), np.uint8)
+    mask[0, :, 0] = 1
+    mask[0, 0, :] = 2
+    mask[0, ny - 1, :] = 4
+    nu, H = (tau - 0.5) / 3.0, nx - 1
+    xs = np.arange(nx) - 0.5 * nx
+    prof = np.where(np.arange(nx) > 0, g / (2.0 * nu) * (H * H / 4.0 - xs ** 2), 0.0)
+    u0 = np.zeros((3, 1, ny, nx))
+    u0[1] = prof
+    w = Workload("obc_conv2d", "D2Q9", (1, ny, nx), storage=storage, collision=collision, tau=(tau, tau),
+                 body=(0.0, g, 0.0), res_rho=((1.0, 1.0), (1.0, 1.0)), **IDEAL)
+    print(f"U about {prof[1:].mean():.3g}", flush=True)
+    out, st, _ = run_pair(oracle_mod, w, mask, np.ones((1, 1, ny, nx)), 400, u0=u0)
+    check_fields(out, storage)
+
+
+@pytest.mark.parametrize("storage", ["F64", "F32"])
+def test_body_force_drainage_with_convective_outlet(oracle_mod, storage):
+    # Sec. 3.4.2: the non-wetting fluid of the inlet buffer is driven into
+    # the wetting-saturated pack by a body force; the far end is a
+    # convective outlet
+    w, mask, rho = inputs.pcsw_pack(n=40, buffer=4, storage=storage, shape=(50, 37, 40), outlet="convective",
+                                    body=2e-4)
+    _RHO[w.name] = rho
+    out, st, _ = run_pair(oracle_mod, w, mask, rho, 300)
+    check_fields(out, storage)
+    check_capillary(oracle_mod, w, mask, st, 300)
