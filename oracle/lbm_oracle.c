@@ -671,7 +671,9 @@ static void stream(const oref_params *p, const geom_t *G, const uint8_t *solid,
  * the bare outward velocity sum_k j_c^k / sum_k rho^k at time t) -- the
  * average-velocity form -- and f_i(x - c, t+1) the population just streamed
  * into the node below x (f_i(x, t) again where that node is not fluid).
- * fold holds f(t), f holds f(t+1) from the plain streaming. */
+ * fold holds f(t), f holds f(t+1) from the plain streaming.
+ * Pinned in the steady limit only (a fluid at rest, a developed flow); the
+ * transient action of U is parity unpinned. */
 static void convective_outlet(const oref_params *p, const geom_t *G, const uint8_t *solid,
                               const work_t *W, const real_t *fold, real_t *f)
 {
