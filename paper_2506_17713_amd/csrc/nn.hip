@@ -2,11 +2,13 @@
 //
 // Convolution as an implicit GEMM on the MFMA matrix cores:
 //   Y[co][p] = sum_k A[co][k] B[k][p],  k = (tap, ci),  B[k][p] = X[ci][p + off(tap)]
-// A wave owns a 32 (co) x 32 (positions) tile and walks K in steps of 8
-// (v_mfma_f32_32x32x8_bf16) or 2 (v_mfma_f32_32x32x2_f32).  Operand lane
-// layout of these instructions: lane l holds A[l % 32][k0 + l / 32 * kw + j]
-// and B[k0 + l / 32 * kw + j][l % 32] (kw = 4 for bf16, 1 for f32), and the
-// accumulator element v of lane l is D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+// BF16: a wave owns a 32 (co) x NT*32 (positions) tile and walks K in steps of
+// 16 (v_mfma_f32_32x32x16_bf16, gfx950), each weight operand serving NT
+// position tiles.  FP32: a wave owns a 32 x 32 tile and walks K in steps of 2
+// (v_mfma_f32_32x32x2_f32).  Operand lane layout: lane l holds
+// A[l % 32][k0 + l / 32 * kw + j] and B[k0 + l / 32 * kw + j][l % 32] (kw = 8
+// for bf16, 1 for f32), and the accumulator element v of lane l is
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
 // Weight gradients are the GEMM dW[co][(ci,tap)] = sum_p dY[co][p] X[ci][p+off]
 // with positions as the reduction dimension, split into chunks whose partial
 // tiles are summed in a fixed order (deterministic).
@@ -18,9 +20,15 @@
 #include "lbm.h"
 #include "lbm_nn.h"
 
+#ifndef LBM_NN_CONV_NT
+#define LBM_NN_CONV_NT 2  // position tiles per wave of the BF16 convolution
+#endif
+
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ short f2bf(float v) {
@@ -30,12 +38,12 @@ __device__ __forceinline__ short f2bf(float v) {
     return (short)(u >> 16);
 }
 
-__host__ __device__ inline int cin_pad_of(int cin, int prec) { return prec == LBM_NN_BF16 ? (cin + 7) / 8 * 8 : (cin + 1) / 2 * 2; }
+__host__ __device__ inline int cin_pad_of(int cin, int prec) { return prec == LBM_NN_BF16 ? (cin + 15) / 16 * 16 : (cin + 1) / 2 * 2; }
 __host__ __device__ inline int cout_pad_of(int cout) { return (cout + 31) / 32 * 32; }
 
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// packed layout: bf16  [tap][cin_pad/4][cout_pad][4] (two 32-bit words per entry)
+// packed layout: bf16  [tap][cin_pad/8][cout_pad][8] (four 32-bit words per entry)
 //                fp32  [tap][cin_pad][cout_pad]
 __global__ void k_pack(const float* __restrict__ W, int cout, int cin, int transpose, int prec,
                        uint32_t* __restrict__ out) {
@@ -53,9 +61,9 @@ __global__ void k_pack(const float* __restrict__ W, int cout, int cin, int trans
         v = transpose ? W[((size_t)ci * cin + co) * 27 + (26 - tap)] : W[((size_t)co * cin + ci) * 27 + tap];
     }
     if (prec == LBM_NN_BF16) {
-        const int cg = ci / 4, j = ci % 4;
+        const int cg = ci / 8, j = ci % 8;
         short* o = reinterpret_cast<short*>(out);
-        o[(((size_t)tap * (cip / 4) + cg) * cop + co) * 4 + j] = f2bf(v);
+        o[(((size_t)tap * (cip / 8) + cg) * cop + co) * 8 + j] = f2bf(v);
     } else {
         reinterpret_cast<float*>(out)[((size_t)tap * cip + ci) * cop + co] = v;
     }
@@ -81,11 +89,11 @@ __global__ void k_act_pack(const float* __restrict__ X, int cin, int cip, int64_
     Xb[i] = v;
 }
 
-template <int PREC>
+// FP32 convolution: one wave per 32 (co) x 32 (positions) tile.
 __global__ void __launch_bounds__(256)
-    k_conv(const float* __restrict__ X, const bf16x4* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
-           const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout, int D,
-           int H, int W, int relu) {
+    k_conv_f32(const float* __restrict__ X, int cin, const uint32_t* __restrict__ packed,
+               const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout, int D,
+               int H, int W, int relu) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int P = D * H * W;
     const int p = (blockIdx.x * 4 + wave) * 32 + (lane & 31);
@@ -94,29 +102,19 @@ __global__ void __launch_bounds__(256)
     const int x = pp % W, y = (pp / W) % H, z = pp / (W * H);
     const int co0 = blockIdx.y * 32;
     const int kq = lane >> 5;
-    const int cip = cin_pad_of(cin, PREC), cop = cout_pad_of(cout);
+    const int cip = cin_pad_of(cin, LBM_NN_FP32), cop = cout_pad_of(cout);
     f32x16 acc;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    const float* wp = reinterpret_cast<const float*>(packed);
     for (int tap = 0; tap < 27; ++tap) {
         const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
         const int q = (wrapc(z + dz, D) * H + wrapc(y + dy, H)) * W + wrapc(x + dx, W);
-        if constexpr (PREC == LBM_NN_BF16) {
-            const bf16x4* wp = reinterpret_cast<const bf16x4*>(packed);
-            const bf16x4 zero = {0, 0, 0, 0};
-            for (int c8 = 0; c8 < cip; c8 += 8) {
-                const bf16x4 a = wp[((size_t)tap * (cip / 4) + c8 / 4 + kq) * cop + co0 + (lane & 31)];
-                const bf16x4 b = pok ? Xb[(size_t)q * (cip / 4) + c8 / 4 + kq] : zero;
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-            }
-        } else {
-            const float* wp = reinterpret_cast<const float*>(packed);
-            for (int c2 = 0; c2 < cip; c2 += 2) {
-                const int ci = c2 + kq;
-                const float a = wp[((size_t)tap * cip + ci) * cop + co0 + (lane & 31)];
-                const float b = (pok && ci < cin) ? X[(size_t)ci * P + q] : 0.0f;
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-            }
+        for (int c2 = 0; c2 < cip; c2 += 2) {
+            const int ci = c2 + kq;
+            const float a = wp[((size_t)tap * cip + ci) * cop + co0 + (lane & 31)];
+            const float b = (pok && ci < cin) ? X[(size_t)ci * P + q] : 0.0f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
         }
     }
     if (!pok) return;
@@ -128,6 +126,91 @@ __global__ void __launch_bounds__(256)
             if (relu) r = r > 0.0f ? r : 0.0f;
             if (skip) r += skip[(size_t)co * P + p];
             Y[(size_t)co * P + p] = r;
+        }
+    }
+}
+
+// BF16 convolution: one wave per 32 (co) x NT*32 (positions) tile, K in steps
+// of 16 channels of one tap.  The weight operand (8 channels of one output
+// channel: 16 bytes) is loaded once for NT MFMAs; each input operand (8
+// channels at one tap position of the channels-innermost copy Xb: 16 bytes) is
+// one load.  The next step's operands are loaded before this step's MFMAs.
+template <int NT>
+__global__ void __launch_bounds__(256)
+    k_conv_bf16(const short* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
+                const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout,
+                int D, int H, int W, int relu) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int P = D * H * W;
+    const int cip = cin_pad_of(cin, LBM_NN_BF16), cop = cout_pad_of(cout);
+    const int co0 = blockIdx.y * 32;
+    const int kq = lane >> 5;
+    const int pbase = (blockIdx.x * 4 + wave) * (32 * NT) + (lane & 31);
+    int px[NT], py[NT], pz[NT];
+    bool pok[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        const int p = pbase + 32 * s;
+        pok[s] = p < P;
+        const int pp = pok[s] ? p : 0;
+        px[s] = pp % W;
+        py[s] = (pp / W) % H;
+        pz[s] = pp / (W * H);
+    }
+    f32x16 acc[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[s][v] = 0.0f;
+    const s16x8* wp = reinterpret_cast<const s16x8*>(packed);
+    const s16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int nc = cip / 16;        // K steps per tap
+    const int nk = 27 * nc;         // K steps in all
+    // operand addresses of K step t: tap = t / nc, channel block c = t % nc
+    int q[NT];
+    auto offsets = [&](int tap) {
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+        for (int s = 0; s < NT; ++s)
+            q[s] = (wrapc(pz[s] + dz, D) * H + wrapc(py[s] + dy, H)) * W + wrapc(px[s] + dx, W);
+    };
+    auto load = [&](int t, s16x8& a, s16x8 (&b)[NT]) {
+        const int tap = t / nc, c = t - tap * nc;
+        a = wp[((size_t)tap * (cip / 8) + 2 * c + kq) * cop + co0 + (lane & 31)];
+#pragma unroll
+        for (int s = 0; s < NT; ++s)
+            b[s] = pok[s] ? *reinterpret_cast<const s16x8*>(Xb + (size_t)q[s] * cip + 16 * c + 8 * kq) : zero;
+    };
+    s16x8 a0, b0[NT];
+    offsets(0);
+    load(0, a0, b0);
+    for (int t = 0; t < nk; ++t) {
+        s16x8 a1, b1[NT];
+        if (t + 1 < nk) {
+            if ((t + 1) % nc == 0) offsets((t + 1) / nc);
+            load(t + 1, a1, b1);
+        }
+#pragma unroll
+        for (int s = 0; s < NT; ++s)
+            acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0),
+                                                             __builtin_bit_cast(bf16x8, b0[s]), acc[s], 0, 0, 0);
+        a0 = a1;
+#pragma unroll
+        for (int s = 0; s < NT; ++s) b0[s] = b1[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        if (!pok[s]) continue;
+        const int p = pbase + 32 * s;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
+            if (co < cout) {
+                float r = acc[s][v] + (bias ? bias[co] : 0.0f);
+                if (relu) r = r > 0.0f ? r : 0.0f;
+                if (skip) r += skip[(size_t)co * P + p];
+                Y[(size_t)co * P + p] = r;
+            }
         }
     }
 }
@@ -505,17 +588,18 @@ int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* b
     const int64_t P = (int64_t)D * H * W;
     if (P * (c_in > c_out ? c_in : c_out) >= (1LL << 31)) return LBM_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
-    dim3 grid((unsigned)((P + 127) / 128), (unsigned)((c_out + 31) / 32));
     if (prec == LBM_NN_BF16) {
         if (!work) return LBM_ERR_ARG;
         const int cip = cin_pad_of(c_in, prec);
         bf16x4* Xb = reinterpret_cast<bf16x4*>(work);
         hipLaunchKernelGGL(k_act_pack, dim3(grid1((int64_t)(cip / 4) * P)), dim3(256), 0, st, X, c_in, cip, P, Xb);
-        hipLaunchKernelGGL(k_conv<LBM_NN_BF16>, grid, dim3(256), 0, st, X, Xb, c_in, packed, bias, skip, Y, c_out,
-                           D, H, W, relu);
-    } else if (prec == LBM_NN_FP32) {
-        hipLaunchKernelGGL(k_conv<LBM_NN_FP32>, grid, dim3(256), 0, st, X, (const bf16x4*)nullptr, c_in, packed,
+        constexpr int NT = LBM_NN_CONV_NT;
+        dim3 grid((unsigned)((P + 128 * NT - 1) / (128 * NT)), (unsigned)((c_out + 31) / 32));
+        hipLaunchKernelGGL(k_conv_bf16<NT>, grid, dim3(256), 0, st, reinterpret_cast<const short*>(Xb), c_in, packed,
                            bias, skip, Y, c_out, D, H, W, relu);
+    } else if (prec == LBM_NN_FP32) {
+        dim3 grid((unsigned)((P + 127) / 128), (unsigned)((c_out + 31) / 32));
+        hipLaunchKernelGGL(k_conv_f32, grid, dim3(256), 0, st, X, c_in, packed, bias, skip, Y, c_out, D, H, W, relu);
     } else {
         return LBM_ERR_ARG;
     }
