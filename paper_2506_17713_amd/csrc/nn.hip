@@ -23,6 +23,9 @@
 #ifndef LBM_NN_CONV_NT
 #define LBM_NN_CONV_NT 2  // position tiles per wave of the BF16 convolution
 #endif
+#ifndef LBM_NN_CONV_LDS
+#define LBM_NN_CONV_LDS 1  // BF16 convolution with the input brick staged in LDS (W >= 32)
+#endif
 
 namespace {
 
@@ -202,6 +205,89 @@ __global__ void __launch_bounds__(256)
     for (int s = 0; s < NT; ++s) {
         if (!pok[s]) continue;
         const int p = pbase + 32 * s;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
+            if (co < cout) {
+                float r = acc[s][v] + (bias ? bias[co] : 0.0f);
+                if (relu) r = r > 0.0f ? r : 0.0f;
+                if (skip) r += skip[(size_t)co * P + p];
+                Y[(size_t)co * P + p] = r;
+            }
+        }
+    }
+}
+
+// BF16 convolution with the input staged in LDS: a workgroup computes a brick
+// of 64 (x) x 2 (y) x 2 (z) positions for 32 output channels (one row of 64
+// positions per wave, two 32-position MFMA tiles).  For each block of 16 input
+// channels it stages the brick with its one-position halo (66 x 4 x 4
+// positions x 32 bytes = 33.8 KB, periodic wrap) in LDS, then every tap takes
+// its input operand there: the 27 taps share one global read of each input.
+constexpr int kBX = 64, kBY = 2, kBZ = 2;
+constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2, kHalo = kHX * kHY * kHZ;
+
+__global__ void __launch_bounds__(256)
+    k_conv_bf16_lds(const short* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
+                    const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout,
+                    int D, int H, int W, int relu) {
+    __shared__ __align__(16) s16x8 sx[kHalo * 2];  // [position][two halves of 8 channels]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int P = D * H * W;
+    const int cip = cin_pad_of(cin, LBM_NN_BF16), cop = cout_pad_of(cout);
+    const int nbx = (W + kBX - 1) / kBX, nby = (H + kBY - 1) / kBY;
+    const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+    const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+    const int co0 = blockIdx.y * 32;
+    const int kq = lane >> 5;
+    const int ly = wave % kBY, lz = wave / kBY;
+    const int y = y0 + ly, z = z0 + lz;
+    bool pok[2];
+    int lx[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        lx[s] = 32 * s + (lane & 31);
+        pok[s] = x0 + lx[s] < W && y < H && z < D;
+    }
+    f32x16 acc[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[s][v] = 0.0f;
+    const s16x8* wp = reinterpret_cast<const s16x8*>(packed);
+    const s16x8* xg = reinterpret_cast<const s16x8*>(Xb);  // [position][cip / 8]
+    const int g8 = cip / 8;
+    for (int c = 0; c < cip / 16; ++c) {
+        __syncthreads();  // the previous block's reads are done
+        for (int i = threadIdx.x; i < kHalo * 2; i += 256) {
+            const int hp = i >> 1, half = i & 1;
+            const int hx = hp % kHX, hy = (hp / kHX) % kHY, hz = hp / (kHX * kHY);
+            const int gx = wrapc(x0 + hx - 1, W), gy = wrapc(y0 + hy - 1, H), gz = wrapc(z0 + hz - 1, D);
+            const int gxx = gx < W ? gx : gx % W;  // bricks wider than the lattice
+            const int gyy = gy < H ? gy : gy % H;
+            const int gzz = gz < D ? gz : gz % D;
+            sx[i] = xg[((size_t)(gzz * H + gyy) * W + gxx) * g8 + 2 * c + half];
+        }
+        __syncthreads();
+        s16x8 a0 = wp[((size_t)0 * g8 + 2 * c + kq) * cop + co0 + (lane & 31)];
+        for (int tap = 0; tap < 27; ++tap) {
+            s16x8 a1;
+            if (tap + 1 < 27) a1 = wp[((size_t)(tap + 1) * g8 + 2 * c + kq) * cop + co0 + (lane & 31)];
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // offsets + 1
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int hp = ((lz + dz) * kHY + (ly + dy)) * kHX + lx[s] + dx;
+                const s16x8 b = sx[2 * hp + kq];
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0),
+                                                                 __builtin_bit_cast(bf16x8, b), acc[s], 0, 0, 0);
+            }
+            a0 = a1;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        if (!pok[s]) continue;
+        const int p = (z * H + y) * W + x0 + lx[s];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
@@ -593,6 +679,14 @@ int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* b
         const int cip = cin_pad_of(c_in, prec);
         bf16x4* Xb = reinterpret_cast<bf16x4*>(work);
         hipLaunchKernelGGL(k_act_pack, dim3(grid1((int64_t)(cip / 4) * P)), dim3(256), 0, st, X, c_in, cip, P, Xb);
+#if LBM_NN_CONV_LDS
+        if (W >= 32) {
+            const unsigned nb = (unsigned)(((W + kBX - 1) / kBX) * ((H + kBY - 1) / kBY) * ((D + kBZ - 1) / kBZ));
+            hipLaunchKernelGGL(k_conv_bf16_lds, dim3(nb, (unsigned)((c_out + 31) / 32)), dim3(256), 0, st,
+                               reinterpret_cast<const short*>(Xb), c_in, packed, bias, skip, Y, c_out, D, H, W, relu);
+            return ok(hipGetLastError());
+        }
+#endif
         constexpr int NT = LBM_NN_CONV_NT;
         dim3 grid((unsigned)((P + 128 * NT - 1) / (128 * NT)), (unsigned)((c_out + 31) / 32));
         hipLaunchKernelGGL(k_conv_bf16<NT>, grid, dim3(256), 0, st, reinterpret_cast<const short*>(Xb), c_in, packed,

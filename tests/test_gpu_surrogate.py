@@ -29,9 +29,12 @@ def ops():
 
 SHAPES = [(1, 16, (8, 6, 10)), (16, 3, (8, 8, 8)), (35, 40, (6, 10, 12)), (64, 64, (4, 4, 4)),
           (128, 128, (4, 6, 8)), (64, 128, (6, 6, 6))]
+# rows of 32 or more positions take the BF16 kernel with the LDS-staged input
+# brick (64 x 2 x 2 positions): ragged bricks in x, y and z, two channel tiles
+WIDE = [(16, 16, (5, 7, 70)), (1, 16, (3, 4, 64)), (24, 40, (4, 6, 32)), (64, 32, (2, 3, 96))]
 
 
-@pytest.mark.parametrize("cin,cout,dhw", SHAPES)
+@pytest.mark.parametrize("cin,cout,dhw", SHAPES + WIDE)
 @pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 2e-2)])
 def test_conv_forward(T, ops, cin, cout, dhw, prec, tol):
     from oracle import nn_ref
@@ -50,7 +53,7 @@ def test_conv_forward(T, ops, cin, cout, dhw, prec, tol):
     assert rel(Y2, nn_ref.conv(X, W)) < tol
 
 
-@pytest.mark.parametrize("cin,cout,dhw", SHAPES)
+@pytest.mark.parametrize("cin,cout,dhw", SHAPES + WIDE)
 @pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 2e-2)])
 def test_conv_data_gradient(T, ops, cin, cout, dhw, prec, tol):
     from oracle import nn_ref
