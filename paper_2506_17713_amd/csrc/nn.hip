@@ -26,6 +26,19 @@
 #ifndef LBM_NN_CONV_LDS
 #define LBM_NN_CONV_LDS 1  // BF16 convolution with the input brick staged in LDS (W >= 32)
 #endif
+// Brick of that kernel: 64 x BRICK_Y x BRICK_Z positions, BRICK_WAVES waves.
+// 64 x 2 x 2 with 4 waves is the fastest measured: 64 x 4 x 2 (4 waves, two
+// rows each) and 64 x 4 x 4 (8 waves) ran 13 % slower despite their smaller
+// halo (fewer resident workgroups, more registers per wave).
+#ifndef LBM_NN_BRICK_Y
+#define LBM_NN_BRICK_Y 2
+#endif
+#ifndef LBM_NN_BRICK_Z
+#define LBM_NN_BRICK_Z 2
+#endif
+#ifndef LBM_NN_BRICK_WAVES
+#define LBM_NN_BRICK_WAVES 4
+#endif
 
 namespace {
 
@@ -218,87 +231,104 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// BF16 convolution with the input staged in LDS: a workgroup computes a brick
-// of 64 (x) x 2 (y) x 2 (z) positions for 32 output channels (one row of 64
-// positions per wave, two 32-position MFMA tiles).  For each block of 16 input
-// channels it stages the brick with its one-position halo (66 x 4 x 4
-// positions x 32 bytes = 33.8 KB, periodic wrap) in LDS, then every tap takes
-// its input operand there: the 27 taps share one global read of each input.
-constexpr int kBX = 64, kBY = 2, kBZ = 2;
-constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2, kHalo = kHX * kHY * kHZ;
+// BF16 convolution with the input staged in LDS: a workgroup of NW waves
+// computes a brick of 64 (x) x BY (y) x BZ (z) positions for 32 output
+// channels (BY * BZ / NW rows of 64 positions per wave, two 32-position MFMA
+// tiles per row).  For each block of 16 input channels it stages the brick with
+// its one-position halo (66 x (BY + 2) x (BZ + 2) positions x 32 bytes,
+// periodic wrap) in LDS, then every tap takes its input operand there: the 27
+// taps share one global read of each input.
+constexpr int kBX = 64, kHX = kBX + 2;
 
-__global__ void __launch_bounds__(256)
+template <int BY, int BZ>
+constexpr int halo_positions() { return kHX * (BY + 2) * (BZ + 2); }
+
+template <int BY, int BZ, int NW>
+__global__ void __launch_bounds__(64 * NW)
     k_conv_bf16_lds(const short* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
                     const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout,
                     int D, int H, int W, int relu) {
-    __shared__ __align__(16) s16x8 sx[kHalo * 2];  // [position][two halves of 8 channels]
+    constexpr int HY = BY + 2, HZ = BZ + 2, HALO = halo_positions<BY, BZ>();
+    constexpr int RW = BY * BZ / NW;  // rows per wave
+    static_assert(RW * NW == BY * BZ, "rows divide among the waves");
+    __shared__ __align__(16) s16x8 sx[HALO * 2];  // [position][two halves of 8 channels]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int P = D * H * W;
     const int cip = cin_pad_of(cin, LBM_NN_BF16), cop = cout_pad_of(cout);
-    const int nbx = (W + kBX - 1) / kBX, nby = (H + kBY - 1) / kBY;
+    const int nbx = (W + kBX - 1) / kBX, nby = (H + BY - 1) / BY;
     const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
-    const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+    const int x0 = bx * kBX, y0 = by * BY, z0 = bz * BZ;
     const int co0 = blockIdx.y * 32;
     const int kq = lane >> 5;
-    const int ly = wave % kBY, lz = wave / kBY;
-    const int y = y0 + ly, z = z0 + lz;
-    bool pok[2];
-    int lx[2];
+    int ly[RW], lz[RW];
+    bool pok[RW][2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        lx[s] = 32 * s + (lane & 31);
-        pok[s] = x0 + lx[s] < W && y < H && z < D;
+    for (int r = 0; r < RW; ++r) {
+        const int row = wave + NW * r;
+        ly[r] = row % BY;
+        lz[r] = row / BY;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+            pok[r][s] = x0 + 32 * s + (lane & 31) < W && y0 + ly[r] < H && z0 + lz[r] < D;
     }
-    f32x16 acc[2];
+    f32x16 acc[RW][2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[s][v] = 0.0f;
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[r][s][v] = 0.0f;
     const s16x8* wp = reinterpret_cast<const s16x8*>(packed);
     const s16x8* xg = reinterpret_cast<const s16x8*>(Xb);  // [position][cip / 8]
     const int g8 = cip / 8;
     for (int c = 0; c < cip / 16; ++c) {
         __syncthreads();  // the previous block's reads are done
-        for (int i = threadIdx.x; i < kHalo * 2; i += 256) {
+        for (int i = threadIdx.x; i < HALO * 2; i += 64 * NW) {
             const int hp = i >> 1, half = i & 1;
-            const int hx = hp % kHX, hy = (hp / kHX) % kHY, hz = hp / (kHX * kHY);
-            const int gx = wrapc(x0 + hx - 1, W), gy = wrapc(y0 + hy - 1, H), gz = wrapc(z0 + hz - 1, D);
-            const int gxx = gx < W ? gx : gx % W;  // bricks wider than the lattice
-            const int gyy = gy < H ? gy : gy % H;
-            const int gzz = gz < D ? gz : gz % D;
-            sx[i] = xg[((size_t)(gzz * H + gyy) * W + gxx) * g8 + 2 * c + half];
+            const int hx = hp % kHX, hy = (hp / kHX) % HY, hz = hp / (kHX * HY);
+            int gx = wrapc(x0 + hx - 1, W), gy = wrapc(y0 + hy - 1, H), gz = wrapc(z0 + hz - 1, D);
+            gx = gx < W ? gx : gx % W;  // bricks wider or taller than the lattice
+            gy = gy < H ? gy : gy % H;
+            gz = gz < D ? gz : gz % D;
+            sx[i] = xg[((size_t)(gz * H + gy) * W + gx) * g8 + 2 * c + half];
         }
         __syncthreads();
+        // the weights stay in global memory (cache hits): staged in LDS as
+        // well they cost a workgroup per CU and ran 15 % slower
         s16x8 a0 = wp[((size_t)0 * g8 + 2 * c + kq) * cop + co0 + (lane & 31)];
         for (int tap = 0; tap < 27; ++tap) {
             s16x8 a1;
             if (tap + 1 < 27) a1 = wp[((size_t)(tap + 1) * g8 + 2 * c + kq) * cop + co0 + (lane & 31)];
             const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // offsets + 1
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int hp = ((lz + dz) * kHY + (ly + dy)) * kHX + lx[s] + dx;
-                const s16x8 b = sx[2 * hp + kq];
-                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0),
-                                                                 __builtin_bit_cast(bf16x8, b), acc[s], 0, 0, 0);
-            }
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int hp = ((lz[r] + dz) * HY + (ly[r] + dy)) * kHX + 32 * s + (lane & 31) + dx;
+                    const s16x8 b = sx[2 * hp + kq];
+                    acc[r][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0),
+                                                                        __builtin_bit_cast(bf16x8, b), acc[r][s], 0, 0, 0);
+                }
             a0 = a1;
         }
     }
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        if (!pok[s]) continue;
-        const int p = (z * H + y) * W + x0 + lx[s];
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
-            if (co < cout) {
-                float r = acc[s][v] + (bias ? bias[co] : 0.0f);
-                if (relu) r = r > 0.0f ? r : 0.0f;
-                if (skip) r += skip[(size_t)co * P + p];
-                Y[(size_t)co * P + p] = r;
+        for (int s = 0; s < 2; ++s) {
+            if (!pok[r][s]) continue;
+            const int p = ((z0 + lz[r]) * H + y0 + ly[r]) * W + x0 + 32 * s + (lane & 31);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
+                if (co < cout) {
+                    float rr = acc[r][s][v] + (bias ? bias[co] : 0.0f);
+                    if (relu) rr = rr > 0.0f ? rr : 0.0f;
+                    if (skip) rr += skip[(size_t)co * P + p];
+                    Y[(size_t)co * P + p] = rr;
+                }
             }
         }
-    }
 }
 
 // Weight gradient partial tiles: one wave per (co block, n block, position chunk),
@@ -681,9 +711,11 @@ int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* b
         hipLaunchKernelGGL(k_act_pack, dim3(grid1((int64_t)(cip / 4) * P)), dim3(256), 0, st, X, c_in, cip, P, Xb);
 #if LBM_NN_CONV_LDS
         if (W >= 32) {
-            const unsigned nb = (unsigned)(((W + kBX - 1) / kBX) * ((H + kBY - 1) / kBY) * ((D + kBZ - 1) / kBZ));
-            hipLaunchKernelGGL(k_conv_bf16_lds, dim3(nb, (unsigned)((c_out + 31) / 32)), dim3(256), 0, st,
-                               reinterpret_cast<const short*>(Xb), c_in, packed, bias, skip, Y, c_out, D, H, W, relu);
+            constexpr int BY = LBM_NN_BRICK_Y, BZ = LBM_NN_BRICK_Z, NW = LBM_NN_BRICK_WAVES;
+            const unsigned nb = (unsigned)(((W + kBX - 1) / kBX) * ((H + BY - 1) / BY) * ((D + BZ - 1) / BZ));
+            hipLaunchKernelGGL((k_conv_bf16_lds<BY, BZ, NW>), dim3(nb, (unsigned)((c_out + 31) / 32)), dim3(64 * NW),
+                               0, st, reinterpret_cast<const short*>(Xb), c_in, packed, bias, skip, Y, c_out, D, H, W,
+                               relu);
             return ok(hipGetLastError());
         }
 #endif
