@@ -258,7 +258,14 @@ def run_adjoint(args) -> dict:
                    "reverse_ms_per_step_est": round(rev_ms, 4), "S": L,
                    # lbm_grad gives dS/dT (absolute temperature); T = T_r T_c
                    "dS_dTr": dT * inputs.load_coexistence()["CS"]["Tc"]},
-        "roofline": None, "cpu_baseline": None,
+        # dominant kernel: the fused forward step (run twice per step: checkpointing
+        # pass and segment recomputation), timed above with events on its stream
+        "roofline": {"bound": "hbm", "achieved": round(algorithmic_bytes(w, solid) / (fwd_ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(algorithmic_bytes(w, solid) / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": algorithmic_bytes(w, solid),
+                     "kernel": "k_step (forward and recompute; about half of the gradient's time)"},
+        "cpu_baseline": None,
     }
 
 
