@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="no GPU work: time the FP64 oracle on the host at the sizes of the parity runs (the "
+                         "128^2 droplet, 64^3 and 128^3 sessile drops, the two-component 64^3 pack crop), on all "
+                         "threads and on one, and print one JSON line per case")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="after the run, two plain device copies of this many GiB (hardware-counter calibration)")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
@@ -215,6 +219,39 @@ def cpu_baseline(budget_s: float, name: str) -> dict:
             "value_1thread": v1, "sample_1thread": f"{k1} steps, {dt1:.1f} s", "cpu": cpu_model()}
 
 
+def cpu_table() -> None:
+    """The FP64 oracle's rate on the host at the sizes of the parity runs:
+    all threads (OMP_NUM_THREADS) and one thread, first step excluded."""
+    import numpy as np
+
+    from oracle import oracle
+    from paper_2506_17713_amd import inputs
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    full = inputs.sphere_pack((400, 400, 400), (8.0, 16.0), 0.35, 0)
+    crop = np.ascontiguousarray(full[:64, :64, :64])
+    cases = [
+        ("D2Q9 BGK droplet 128^2 (full configuration)", make_workload("droplet2d", 128, "F64", "BGK")[:3], 2000, 200),
+        ("D3Q19 MRT sessile drop 64^3", make_workload("sessile", 64, "F64", "MRT")[:3], 100, 10),
+        ("D3Q19 MRT sessile drop 128^3", make_workload("sessile", 128, "F64", "MRT")[:3], 100, 5),
+        ("D3Q19 two-component pack, 64^3 crop of the 400^3 pack",
+         inputs.two_component_pack(shape=(64, 64, 64), storage="F64", solid=crop), 100, 10),
+    ]
+    for name, (w, solid, rho), k_all, k_one in cases:
+        st = oracle.State(w, solid, rho)
+        row = {"case": name, "cpu": cpu_model(), "cores": cores, "kind": "oracle", "unit": "MLUPS"}
+        for threads, k in ((cores, k_all), (1, k_one)):
+            oracle.set_threads(threads)
+            st.step(1)
+            t0 = time.perf_counter()
+            st.step(k)
+            dt = time.perf_counter() - t0
+            row["value" if threads == cores else "value_1thread"] = w.nc * w.N * k / dt / 1e6
+            row["steps" if threads == cores else "steps_1thread"] = k
+        oracle.set_threads(cores)
+        print(json.dumps(row), flush=True)
+
+
 def run_adjoint(args) -> dict:
     """Gradient of the smooth non-wetting saturation after `steps` (default
     1000) FP32 steps of the 128^3 single-component pack (porosity 0.4, CS at
@@ -349,6 +386,9 @@ def main():
     args = parse()
     if args.record_traffic:
         print(json.dumps(record_traffic(*args.record_traffic), indent=1))
+        return
+    if args.cpu_table:
+        cpu_table()
         return
     if args.steps is None:
         args.steps = {"adjoint": 1000, "surrogate": 20}.get(args.workload, 500)
