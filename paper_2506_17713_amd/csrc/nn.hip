@@ -26,6 +26,9 @@
 #ifndef LBM_NN_CONV_LDS
 #define LBM_NN_CONV_LDS 1  // BF16 convolution with the input brick staged in LDS (W >= 32)
 #endif
+#ifndef LBM_NN_CONV_16ROW
+#define LBM_NN_CONV_16ROW 1  // 16-row MFMA tiles for layers of at most 16 output channels
+#endif
 // Brick of that kernel: 64 x BRICK_Y x BRICK_Z positions, BRICK_WAVES waves.
 // 64 x 2 x 2 with 4 waves is the fastest measured: 64 x 4 x 2 (4 waves, two
 // rows each) and 64 x 4 x 4 (8 waves) ran 13 % slower despite their smaller
@@ -46,6 +49,7 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ short f2bf(float v) {
     uint32_t u = __float_as_uint(v);
@@ -86,23 +90,37 @@ __global__ void k_pack(const float* __restrict__ W, int cout, int cin, int trans
 }
 
 // Input of a BF16 convolution converted once: Xb[p][cin_pad] (BF16, channels
-// innermost, zero beyond cin), so that a lane's B operand (4 channels at one
-// position) is one 8-byte load.  Thread i converts channel group g = i % G of
-// position p = i / G: consecutive lanes write consecutive 8-byte words, and
-// the lanes of one group read consecutive positions of a channel plane.
-__global__ void k_act_pack(const float* __restrict__ X, int cin, int cip, int64_t P, bf16x4* __restrict__ Xb) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int G = cip / 4;
-    if (i >= (int64_t)G * P) return;
-    const int64_t p = i / G;
-    const int g = (int)(i - p * G);
-    bf16x4 v;
+// innermost, zero beyond cin), so that a lane's B operand (8 channels at one
+// position) is one 16-byte load.  A block transposes 64 positions through LDS:
+// it reads each channel plane's 64 positions as one 256-byte row and writes
+// the block's 64 x cin_pad values as one contiguous run of 16-byte words.
+constexpr int kPackPos = 64, kPackMaxC = 128;
+
+__global__ void __launch_bounds__(256) k_act_pack(const float* __restrict__ X, int cin, int cip, int64_t P,
+                                                  s16x8* __restrict__ Xb) {
+    __shared__ short sh[kPackMaxC][kPackPos + 2];  // [channel][position] (+2: fewer bank conflicts)
+    const int64_t p0 = (int64_t)blockIdx.x * kPackPos;
+    const int t = threadIdx.x, lp = t % kPackPos;
+    const bool ok = p0 + lp < P;
+    const int G = cip / 8;
+    for (int cb = 0; cb < cip; cb += kPackMaxC) {  // channel chunks of at most 128
+        const int nc = cip - cb < kPackMaxC ? cip - cb : kPackMaxC;
+        if (cb > 0) __syncthreads();
+        for (int cl = t / kPackPos; cl < nc; cl += 256 / kPackPos) {
+            const int ci = cb + cl;
+            sh[cl][lp] = (ci < cin && ok) ? f2bf(X[(size_t)ci * P + p0 + lp]) : (short)0;
+        }
+        __syncthreads();
+        const int Gc = nc / 8;
+        for (int w = t; w < kPackPos * Gc; w += 256) {
+            const int pos = w / Gc, g = w % Gc;
+            if (p0 + pos >= P) continue;
+            s16x8 v;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int ci = 4 * g + j;
-        v[j] = ci < cin ? f2bf(X[(size_t)ci * P + p]) : (short)0;
+            for (int j = 0; j < 8; ++j) v[j] = sh[8 * g + j][pos];
+            Xb[(size_t)(p0 + pos) * G + cb / 8 + g] = v;
+        }
     }
-    Xb[i] = v;
 }
 
 // FP32 convolution: one wave per 32 (co) x 32 (positions) tile.
@@ -331,6 +349,92 @@ __global__ void __launch_bounds__(64 * NW)
         }
 }
 
+// The same brick for layers of at most 16 output channels, on 16-row tiles
+// (v_mfma_f32_16x16x32_bf16): lane l holds A[l % 16][k0 + 8 (l / 16) + j] and
+// B[k0 + 8 (l / 16) + j][l % 16], and the accumulator element v of lane l is
+// D[4 (l / 16) + v][l % 16].  A K step of 32 covers (tap, 8-channel half)
+// pairs 4 t .. 4 t + 3 of the 16-channel block, i.e. two taps: 14 steps per
+// block (the last half empty) instead of 27, and each weight load feeds the
+// four 16-position tiles of the wave's row.
+template <int BY, int BZ, int NW>
+__global__ void __launch_bounds__(64 * NW)
+    k_conv_bf16_lds16(const short* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
+                      const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout,
+                      int D, int H, int W, int relu) {
+    constexpr int HY = BY + 2, HALO = halo_positions<BY, BZ>();
+    static_assert(BY * BZ == NW, "one row per wave");
+    __shared__ __align__(16) s16x8 sx[HALO * 2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int P = D * H * W;
+    const int cip = cin_pad_of(cin, LBM_NN_BF16), cop = cout_pad_of(cout);
+    const int nbx = (W + kBX - 1) / kBX, nby = (H + BY - 1) / BY;
+    const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+    const int x0 = bx * kBX, y0 = by * BY, z0 = bz * BZ;
+    const int g = lane >> 4, col = lane & 15;
+    const int ly = wave % BY, lz = wave / BY;
+    const bool rok = y0 + ly < H && z0 + lz < D;
+    f32x4 acc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[s][v] = 0.0f;
+    const s16x8* wp = reinterpret_cast<const s16x8*>(packed);
+    const s16x8* xg = reinterpret_cast<const s16x8*>(Xb);
+    const int g8 = cip / 8;
+    const s16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < cip / 16; ++c) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < HALO * 2; i += 64 * NW) {
+            const int hp = i >> 1, half = i & 1;
+            const int hx = hp % kHX, hy = (hp / kHX) % HY, hz = hp / (kHX * HY);
+            int gx = wrapc(x0 + hx - 1, W), gy = wrapc(y0 + hy - 1, H), gz = wrapc(z0 + hz - 1, D);
+            gx = gx < W ? gx : gx % W;
+            gy = gy < H ? gy : gy % H;
+            gz = gz < D ? gz : gz % D;
+            sx[i] = xg[((size_t)(gz * H + gy) * W + gx) * g8 + 2 * c + half];
+        }
+        __syncthreads();
+        // this lane's (tap, half) of K step t is pair 4 t + g; pairs 54, 55 are empty
+        auto wload = [&](int t) {
+            const int pr = 4 * t + g;
+            return pr < 54 ? wp[((size_t)(pr >> 1) * g8 + 2 * c + (pr & 1)) * cop + col] : zero;
+        };
+        s16x8 a0 = wload(0);
+        for (int t = 0; t < 14; ++t) {
+            s16x8 a1;
+            if (t + 1 < 14) a1 = wload(t + 1);
+            const int pr = 4 * t + g;
+            const int tap = pr < 54 ? pr >> 1 : 26, half = pr & 1;
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;  // offsets + 1
+            const int hrow = ((lz + dz) * HY + (ly + dy)) * kHX + dx + col;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const s16x8 b = sx[2 * (hrow + 16 * s) + half];
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a0),
+                                                                 __builtin_bit_cast(bf16x8, b), acc[s], 0, 0, 0);
+            }
+            a0 = a1;
+        }
+    }
+    if (!rok) return;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int x = x0 + 16 * s + col;
+        if (x >= W) continue;
+        const int p = ((z0 + lz) * H + y0 + ly) * W + x;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int co = 4 * g + v;
+            if (co < cout) {
+                float r = acc[s][v] + (bias ? bias[co] : 0.0f);
+                if (relu) r = r > 0.0f ? r : 0.0f;
+                if (skip) r += skip[(size_t)co * P + p];
+                Y[(size_t)co * P + p] = r;
+            }
+        }
+    }
+}
+
 // Weight gradient partial tiles: one wave per (co block, n block, position chunk),
 // n = ci * 27 + tap.
 // FP32 -> BF16 (round to nearest even), elementwise.
@@ -466,14 +570,23 @@ __global__ void k_pool_bwd(const float* __restrict__ dY, int c, int D, int H, in
 }
 
 // fine index over [c][2D][2H][2W], X coarse [c][D][H][W]
+// One thread per coarse element: it writes its 2 x 2 x 2 fine copies as four
+// 8-byte pairs (coalesced along x).
 __global__ void k_up(const float* __restrict__ X, int c, int D, int H, int W, float* __restrict__ Y) {
-    const int64_t total = (int64_t)c * 8 * D * H * W;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int Wf = 2 * W, Hf = 2 * H, Df = 2 * D;
-    const int x = i % Wf, y = (i / Wf) % Hf, z = (i / ((int64_t)Wf * Hf)) % Df;
-    const int64_t ch = i / ((int64_t)Wf * Hf * Df);
-    Y[i] = X[(((size_t)ch * D + z / 2) * H + y / 2) * W + x / 2];
+    if (i >= (int64_t)c * D * H * W) return;
+    const int x = (int)(i % W), y = (int)((i / W) % H);
+    const int64_t zc = i / ((int64_t)W * H);  // channel * D + z
+    const float v = X[i];
+    const float2 vv = make_float2(v, v);
+    const int Wf = 2 * W, Hf = 2 * H;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const size_t row = ((size_t)(2 * zc + dz) * Hf + 2 * y + dy) * Wf;
+            *reinterpret_cast<float2*>(Y + row + 2 * x) = vv;
+        }
 }
 
 // coarse index over [c][D][H][W], dY fine
@@ -707,12 +820,23 @@ int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* b
     if (prec == LBM_NN_BF16) {
         if (!work) return LBM_ERR_ARG;
         const int cip = cin_pad_of(c_in, prec);
-        bf16x4* Xb = reinterpret_cast<bf16x4*>(work);
-        hipLaunchKernelGGL(k_act_pack, dim3(grid1((int64_t)(cip / 4) * P)), dim3(256), 0, st, X, c_in, cip, P, Xb);
+        s16x8* Xb = reinterpret_cast<s16x8*>(work);
+        hipLaunchKernelGGL(k_act_pack, dim3((unsigned)((P + kPackPos - 1) / kPackPos)), dim3(256), 0, st, X, c_in,
+                           cip, P, Xb);
 #if LBM_NN_CONV_LDS
         if (W >= 32) {
             constexpr int BY = LBM_NN_BRICK_Y, BZ = LBM_NN_BRICK_Z, NW = LBM_NN_BRICK_WAVES;
             const unsigned nb = (unsigned)(((W + kBX - 1) / kBX) * ((H + BY - 1) / BY) * ((D + BZ - 1) / BZ));
+#if LBM_NN_CONV_16ROW
+            if constexpr (BY * BZ == NW) {
+                if (c_out <= 16) {
+                    hipLaunchKernelGGL((k_conv_bf16_lds16<BY, BZ, NW>), dim3(nb), dim3(64 * NW), 0, st,
+                                       reinterpret_cast<const short*>(Xb), c_in, packed, bias, skip, Y, c_out, D, H,
+                                       W, relu);
+                    return ok(hipGetLastError());
+                }
+            }
+#endif
             hipLaunchKernelGGL((k_conv_bf16_lds<BY, BZ, NW>), dim3(nb, (unsigned)((c_out + 31) / 32)), dim3(64 * NW),
                                0, st, reinterpret_cast<const short*>(Xb), c_in, packed, bias, skip, Y, c_out, D, H, W,
                                relu);
@@ -815,7 +939,7 @@ int lbm_nn_pool_bwd(const float* dY, int c, int D, int H, int W, float* dX, int 
 }
 
 int lbm_nn_up(const float* X, int c, int D, int H, int W, float* Y, void* stream) {
-    const int64_t n = (int64_t)c * 8 * D * H * W;
+    const int64_t n = (int64_t)c * D * H * W;
     hipLaunchKernelGGL(k_up, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, X, c, D, H, W, Y);
     return ok(hipGetLastError());
 }

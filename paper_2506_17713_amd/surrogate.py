@@ -88,6 +88,14 @@ class Surrogate:
             tape.append(("add", a, s, y))
         return y
 
+    def _conv_add(self, name, x, s, tape):
+        """relu(conv(x)) + s.  Inference adds the skip in the convolution's
+        epilogue (the same operations in the same order); training keeps the
+        two steps, whose intermediate the backward pass reads."""
+        if tape is not None:
+            return self._add(self._conv(name, x, True, tape), s, tape)
+        return nn.conv(x, self.pk[name], self.W[name].shape[0], bias=self.b[name], skip=s, relu=True, prec=self.prec)
+
     def forward(self, mask: torch.Tensor, tape=None) -> torch.Tensor:
         """mask: float32 [1, D, H, W] (1 = pore).  D, H, W divisible by 8."""
         c = self._conv
@@ -99,11 +107,11 @@ class Surrogate:
         s2 = c("enc2b", a, True, tape)
         a = c("bota", self._pool(s2, tape), True, tape)
         a = c("botb", a, True, tape)
-        a = self._add(c("dec2a", self._up(a, tape), True, tape), s2, tape)
+        a = self._conv_add("dec2a", self._up(a, tape), s2, tape)
         a = c("dec2b", a, True, tape)
-        a = self._add(c("dec1a", self._up(a, tape), True, tape), s1, tape)
+        a = self._conv_add("dec1a", self._up(a, tape), s1, tape)
         a = c("dec1b", a, True, tape)
-        a = self._add(c("dec0a", self._up(a, tape), True, tape), s0, tape)
+        a = self._conv_add("dec0a", self._up(a, tape), s0, tape)
         a = c("dec0b", a, True, tape)
         return c("head", a, False, tape)
 

@@ -31,7 +31,7 @@ SHAPES = [(1, 16, (8, 6, 10)), (16, 3, (8, 8, 8)), (35, 40, (6, 10, 12)), (64, 6
           (128, 128, (4, 6, 8)), (64, 128, (6, 6, 6))]
 # rows of 32 or more positions take the BF16 kernel with the LDS-staged input
 # brick (64 x 2 x 2 positions): ragged bricks in x, y and z, two channel tiles
-WIDE = [(16, 16, (5, 7, 70)), (1, 16, (3, 4, 64)), (24, 40, (4, 6, 32)), (64, 32, (2, 3, 96))]
+WIDE = [(16, 16, (5, 7, 70)), (1, 16, (3, 4, 64)), (24, 40, (4, 6, 32)), (64, 32, (2, 3, 96)), (136, 8, (2, 3, 40))]
 
 
 @pytest.mark.parametrize("cin,cout,dhw", SHAPES + WIDE)
@@ -321,3 +321,18 @@ def test_symmetry_maps_steady_solutions_to_steady_solutions(T, ops):
         err = float(np.abs(t_aug.astype(np.float64) - t2).max() / np.abs(t2).max())
         print(f"symmetry a={a} shift={shift} flip={flip} swap={swap}: {err:.2e}")
         assert err < tol, (a, shift, flip, swap, err)
+
+
+def test_inference_forward_equals_the_taped_forward(T, ops):
+    """The inference forward (skip additions fused into the convolutions'
+    epilogue) and the taped training forward (separate additions) give the
+    same output bitwise, on a 16 x 16 x 64 mask whose finest rows take the
+    LDS-staged convolutions."""
+    from paper_2506_17713_amd.surrogate import Surrogate
+
+    model = Surrogate(prec=ops.BF16, seed=3)
+    rng = np.random.default_rng(5)
+    mask = T.tensor((rng.uniform(size=(1, 16, 16, 64)) < 0.6).astype(np.float32), device="cuda")
+    y0 = model.forward(mask)
+    y1 = model.forward(mask, tape=[])
+    assert T.equal(y0, y1)
