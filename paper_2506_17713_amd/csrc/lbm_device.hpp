@@ -588,6 +588,9 @@ __device__ __forceinline__ R nonfluid_rho(const StepArgs<R>& P, uint32_t word, i
 #ifndef LBM_DEV_RING
 #define LBM_DEV_RING 1
 #endif
+#ifndef LBM_ISSUE_PRIO
+#define LBM_ISSUE_PRIO 3  // wave priority while a plane's loads are issued together
+#endif
 #ifndef LBM_WAVES_1C_DEV
 #define LBM_WAVES_1C_DEV 3
 #endif
@@ -812,11 +815,17 @@ __global__ void __launch_bounds__(TA* TB) __attribute__((amdgpu_waves_per_eu(wav
         // overlapped own-node and halo loads, which costs more than the few
         // solid lanes of its workloads save)
         const bool own_fluid = NC == 1 || !(wo & 1u);
+        // While it issues the plane's loads together the wave runs at raised
+        // priority, so that they leave before other waves' arithmetic (one
+        // component: 1.5 % faster; the sequential two-component pulls ran 26 %
+        // slower with it).
+        if constexpr (OVERLAP) __builtin_amdgcn_s_setprio(LBM_ISSUE_PRIO);
         if (own_fluid) po.issue(P, own_a, own_b, c, wo);
         if constexpr (OVERLAP) {
 #pragma unroll
             for (int j = 0; j < HPT; ++j)
                 if (need(j)) ph[j].issue(P, h_a[j], h_b[j], c, wh[j]);
+            __builtin_amdgcn_s_setprio(0);
         }
         if constexpr (RSR) rs_store(cp + 2, rsn);
         if (own_fluid) po.finish(P, own_a, own_b, c, wo, fo);
