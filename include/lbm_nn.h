@@ -50,6 +50,20 @@ size_t lbm_nn_conv_work_bytes(int c_in, int D, int H, int W, int prec);
 int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* bias, const float* skip,
                 float* Y, int c_out, int D, int H, int W, int relu, int prec, void* work, void* stream);
 
+/* lbm_nn_conv in BF16 for chains of convolutions (inference): the input is
+ * either X (FP32, converted into work as lbm_nn_conv does) or xb, already in
+ * the work layout (BF16 [P][c_in padded to 16], channels innermost: the
+ * yb_next of the producing call); the output goes to Y (FP32) and / or
+ * yb_next, the same values in the work layout of a c_out-channel input
+ * (lbm_nn_conv_work_bytes(c_out, D, H, W, LBM_NN_BF16) bytes, padding
+ * channels zero), so the next convolution skips the conversion and no FP32
+ * tensor needs to exist between two convolutions.  X or xb, and Y or
+ * yb_next, must be given; work is needed only with X.
+ * Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
+int lbm_nn_conv_x(const float* X, const void* xb, int c_in, const uint32_t* packed, const float* bias,
+                  const float* skip, float* Y, void* yb_next, int c_out, int D, int H, int W, int relu, void* work,
+                  void* stream);
+
 /* dW[co][ci][t] = sum_p dY[co][p] X[ci][p + off(t)] (overwrites dW).
  * partial: device scratch of lbm_nn_wgrad_partial_words(c_out, c_in, D, H, W) floats (tile partials, and
  * for BF16 the operands converted once). */

@@ -63,6 +63,17 @@ __host__ __device__ inline int cout_pad_of(int cout) { return (cout + 31) / 32 *
 
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Four consecutive output channels co .. co + 3 of position p into the BF16
+// channels-innermost copy yb[p][cop16] that the next convolution reads
+// (channels at or beyond cout written as zero).
+__device__ __forceinline__ void store_yb4(short* __restrict__ yb, int cop16, int p, int co, int cout, const float (&r)[4]) {
+    if (co >= cop16) return;
+    bf16x4 v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = co + j < cout ? f2bf(r[j]) : (short)0;
+    *reinterpret_cast<bf16x4*>(yb + (size_t)p * cop16 + co) = v;
+}
+
 // packed layout: bf16  [tap][cin_pad/8][cout_pad][8] (four 32-bit words per entry)
 //                fp32  [tap][cin_pad][cout_pad]
 __global__ void k_pack(const float* __restrict__ W, int cout, int cin, int transpose, int prec,
@@ -123,6 +134,31 @@ __global__ void __launch_bounds__(256) k_act_pack(const float* __restrict__ X, i
     }
 }
 
+// Epilogue of a 32-row tile at position p: bias, activation, skip; the FP32
+// output Y[co][p] and / or the BF16 channels-innermost copy (either may be NULL).
+__device__ __forceinline__ void epilogue32(const f32x16& acc, int p, int P, int co0, int kq, int cout,
+                                           const float* __restrict__ bias, const float* __restrict__ skip, int relu,
+                                           float* __restrict__ Y, short* __restrict__ yb) {
+    const int cop16 = (cout + 15) / 16 * 16;
+#pragma unroll
+    for (int vg = 0; vg < 4; ++vg) {
+        float r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = co0 + 8 * vg + 4 * kq + j;
+            r[j] = 0.0f;
+            if (co < cout) {
+                float t = acc[4 * vg + j] + (bias ? bias[co] : 0.0f);
+                if (relu) t = t > 0.0f ? t : 0.0f;
+                if (skip) t += skip[(size_t)co * P + p];
+                r[j] = t;
+                if (Y) Y[(size_t)co * P + p] = t;
+            }
+        }
+        if (yb) store_yb4(yb, cop16, p, co0 + 8 * vg + 4 * kq, cout, r);
+    }
+}
+
 // FP32 convolution: one wave per 32 (co) x 32 (positions) tile.
 __global__ void __launch_bounds__(256)
     k_conv_f32(const float* __restrict__ X, int cin, const uint32_t* __restrict__ packed,
@@ -172,8 +208,8 @@ __global__ void __launch_bounds__(256)
 template <int NT>
 __global__ void __launch_bounds__(256)
     k_conv_bf16(const short* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
-                const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout,
-                int D, int H, int W, int relu) {
+                const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y,
+                short* __restrict__ yb, int cout, int D, int H, int W, int relu) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int P = D * H * W;
     const int cip = cin_pad_of(cin, LBM_NN_BF16), cop = cout_pad_of(cout);
@@ -236,16 +272,7 @@ __global__ void __launch_bounds__(256)
     for (int s = 0; s < NT; ++s) {
         if (!pok[s]) continue;
         const int p = pbase + 32 * s;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
-            if (co < cout) {
-                float r = acc[s][v] + (bias ? bias[co] : 0.0f);
-                if (relu) r = r > 0.0f ? r : 0.0f;
-                if (skip) r += skip[(size_t)co * P + p];
-                Y[(size_t)co * P + p] = r;
-            }
-        }
+        epilogue32(acc[s], p, P, co0, kq, cout, bias, skip, relu, Y, yb);
     }
 }
 
@@ -264,8 +291,8 @@ constexpr int halo_positions() { return kHX * (BY + 2) * (BZ + 2); }
 template <int BY, int BZ, int NW>
 __global__ void __launch_bounds__(64 * NW)
     k_conv_bf16_lds(const short* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
-                    const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout,
-                    int D, int H, int W, int relu) {
+                    const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y,
+                    short* __restrict__ yb, int cout, int D, int H, int W, int relu) {
     constexpr int HY = BY + 2, HZ = BZ + 2, HALO = halo_positions<BY, BZ>();
     constexpr int RW = BY * BZ / NW;  // rows per wave
     static_assert(RW * NW == BY * BZ, "rows divide among the waves");
@@ -336,16 +363,7 @@ __global__ void __launch_bounds__(64 * NW)
         for (int s = 0; s < 2; ++s) {
             if (!pok[r][s]) continue;
             const int p = ((z0 + lz[r]) * H + y0 + ly[r]) * W + x0 + 32 * s + (lane & 31);
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
-                if (co < cout) {
-                    float rr = acc[r][s][v] + (bias ? bias[co] : 0.0f);
-                    if (relu) rr = rr > 0.0f ? rr : 0.0f;
-                    if (skip) rr += skip[(size_t)co * P + p];
-                    Y[(size_t)co * P + p] = rr;
-                }
-            }
+            epilogue32(acc[r][s], p, P, co0, kq, cout, bias, skip, relu, Y, yb);
         }
 }
 
@@ -359,8 +377,8 @@ __global__ void __launch_bounds__(64 * NW)
 template <int BY, int BZ, int NW>
 __global__ void __launch_bounds__(64 * NW)
     k_conv_bf16_lds16(const short* __restrict__ Xb, int cin, const uint32_t* __restrict__ packed,
-                      const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y, int cout,
-                      int D, int H, int W, int relu) {
+                      const float* __restrict__ bias, const float* __restrict__ skip, float* __restrict__ Y,
+                      short* __restrict__ yb, int cout, int D, int H, int W, int relu) {
     constexpr int HY = BY + 2, HALO = halo_positions<BY, BZ>();
     static_assert(BY * BZ == NW, "one row per wave");
     __shared__ __align__(16) s16x8 sx[HALO * 2];
@@ -422,16 +440,20 @@ __global__ void __launch_bounds__(64 * NW)
         const int x = x0 + 16 * s + col;
         if (x >= W) continue;
         const int p = ((z0 + lz) * H + y0 + ly) * W + x;
+        float r[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int co = 4 * g + v;
+            r[v] = 0.0f;
             if (co < cout) {
-                float r = acc[s][v] + (bias ? bias[co] : 0.0f);
-                if (relu) r = r > 0.0f ? r : 0.0f;
-                if (skip) r += skip[(size_t)co * P + p];
-                Y[(size_t)co * P + p] = r;
+                float t = acc[s][v] + (bias ? bias[co] : 0.0f);
+                if (relu) t = t > 0.0f ? t : 0.0f;
+                if (skip) t += skip[(size_t)co * P + p];
+                r[v] = t;
+                if (Y) Y[(size_t)co * P + p] = t;
             }
         }
+        if (yb) store_yb4(yb, 16, p, 4 * g, cout, r);
     }
 }
 
@@ -811,6 +833,48 @@ size_t lbm_nn_conv_work_bytes(int c_in, int D, int H, int W, int prec) {
     return (size_t)D * H * W * cin_pad_of(c_in, prec) * 2;
 }
 
+}  // extern "C"
+
+// BF16 convolution from the channels-innermost input Xb: the LDS-staged
+// kernels for rows of 32 or more positions (16-row tiles up to 16 output
+// channels), the global-operand kernel otherwise.
+static hipError_t conv_bf16_launch(const short* Xb, int c_in, const uint32_t* packed, const float* bias,
+                                   const float* skip, float* Y, short* yb, int c_out, int D, int H, int W, int relu,
+                                   hipStream_t st) {
+    const int64_t P = (int64_t)D * H * W;
+#if LBM_NN_CONV_LDS
+    if (W >= 32) {
+        constexpr int BY = LBM_NN_BRICK_Y, BZ = LBM_NN_BRICK_Z, NW = LBM_NN_BRICK_WAVES;
+        const unsigned nb = (unsigned)(((W + kBX - 1) / kBX) * ((H + BY - 1) / BY) * ((D + BZ - 1) / BZ));
+#if LBM_NN_CONV_16ROW
+        if constexpr (BY * BZ == NW) {
+            if (c_out <= 16) {
+                hipLaunchKernelGGL((k_conv_bf16_lds16<BY, BZ, NW>), dim3(nb), dim3(64 * NW), 0, st, Xb, c_in, packed,
+                                   bias, skip, Y, yb, c_out, D, H, W, relu);
+                return hipGetLastError();
+            }
+        }
+#endif
+        hipLaunchKernelGGL((k_conv_bf16_lds<BY, BZ, NW>), dim3(nb, (unsigned)((c_out + 31) / 32)), dim3(64 * NW), 0,
+                           st, Xb, c_in, packed, bias, skip, Y, yb, c_out, D, H, W, relu);
+        return hipGetLastError();
+    }
+#endif
+    constexpr int NT = LBM_NN_CONV_NT;
+    dim3 grid((unsigned)((P + 128 * NT - 1) / (128 * NT)), (unsigned)((c_out + 31) / 32));
+    hipLaunchKernelGGL(k_conv_bf16<NT>, grid, dim3(256), 0, st, Xb, c_in, packed, bias, skip, Y, yb, c_out, D, H, W,
+                       relu);
+    return hipGetLastError();
+}
+
+static void act_pack_launch(const float* X, int c_in, int64_t P, void* work, hipStream_t st) {
+    const int cip = cin_pad_of(c_in, LBM_NN_BF16);
+    hipLaunchKernelGGL(k_act_pack, dim3((unsigned)((P + kPackPos - 1) / kPackPos)), dim3(256), 0, st, X, c_in, cip,
+                       P, reinterpret_cast<s16x8*>(work));
+}
+
+extern "C" {
+
 int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* bias, const float* skip, float* Y,
                 int c_out, int D, int H, int W, int relu, int prec, void* work, void* stream) {
     if (!X || !packed || !Y || c_in < 1 || c_out < 1 || D < 1 || H < 1 || W < 1) return LBM_ERR_ARG;
@@ -819,34 +883,9 @@ int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* b
     hipStream_t st = (hipStream_t)stream;
     if (prec == LBM_NN_BF16) {
         if (!work) return LBM_ERR_ARG;
-        const int cip = cin_pad_of(c_in, prec);
-        s16x8* Xb = reinterpret_cast<s16x8*>(work);
-        hipLaunchKernelGGL(k_act_pack, dim3((unsigned)((P + kPackPos - 1) / kPackPos)), dim3(256), 0, st, X, c_in,
-                           cip, P, Xb);
-#if LBM_NN_CONV_LDS
-        if (W >= 32) {
-            constexpr int BY = LBM_NN_BRICK_Y, BZ = LBM_NN_BRICK_Z, NW = LBM_NN_BRICK_WAVES;
-            const unsigned nb = (unsigned)(((W + kBX - 1) / kBX) * ((H + BY - 1) / BY) * ((D + BZ - 1) / BZ));
-#if LBM_NN_CONV_16ROW
-            if constexpr (BY * BZ == NW) {
-                if (c_out <= 16) {
-                    hipLaunchKernelGGL((k_conv_bf16_lds16<BY, BZ, NW>), dim3(nb), dim3(64 * NW), 0, st,
-                                       reinterpret_cast<const short*>(Xb), c_in, packed, bias, skip, Y, c_out, D, H,
-                                       W, relu);
-                    return ok(hipGetLastError());
-                }
-            }
-#endif
-            hipLaunchKernelGGL((k_conv_bf16_lds<BY, BZ, NW>), dim3(nb, (unsigned)((c_out + 31) / 32)), dim3(64 * NW),
-                               0, st, reinterpret_cast<const short*>(Xb), c_in, packed, bias, skip, Y, c_out, D, H, W,
-                               relu);
-            return ok(hipGetLastError());
-        }
-#endif
-        constexpr int NT = LBM_NN_CONV_NT;
-        dim3 grid((unsigned)((P + 128 * NT - 1) / (128 * NT)), (unsigned)((c_out + 31) / 32));
-        hipLaunchKernelGGL(k_conv_bf16<NT>, grid, dim3(256), 0, st, reinterpret_cast<const short*>(Xb), c_in, packed,
-                           bias, skip, Y, c_out, D, H, W, relu);
+        act_pack_launch(X, c_in, P, work, st);
+        return ok(conv_bf16_launch(reinterpret_cast<const short*>(work), c_in, packed, bias, skip, Y, nullptr, c_out,
+                                   D, H, W, relu, st));
     } else if (prec == LBM_NN_FP32) {
         dim3 grid((unsigned)((P + 127) / 128), (unsigned)((c_out + 31) / 32));
         hipLaunchKernelGGL(k_conv_f32, grid, dim3(256), 0, st, X, c_in, packed, bias, skip, Y, c_out, D, H, W, relu);
@@ -854,6 +893,23 @@ int lbm_nn_conv(const float* X, int c_in, const uint32_t* packed, const float* b
         return LBM_ERR_ARG;
     }
     return ok(hipGetLastError());
+}
+
+int lbm_nn_conv_x(const float* X, const void* xb, int c_in, const uint32_t* packed, const float* bias,
+                  const float* skip, float* Y, void* yb_next, int c_out, int D, int H, int W, int relu, void* work,
+                  void* stream) {
+    if ((!X && !xb) || !packed || (!Y && !yb_next) || c_in < 1 || c_out < 1 || D < 1 || H < 1 || W < 1)
+        return LBM_ERR_ARG;
+    const int64_t P = (int64_t)D * H * W;
+    if (P * (c_in > c_out ? c_in : c_out) >= (1LL << 31)) return LBM_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (!xb) {
+        if (!work) return LBM_ERR_ARG;
+        act_pack_launch(X, c_in, P, work, st);
+        xb = work;
+    }
+    return ok(conv_bf16_launch(reinterpret_cast<const short*>(xb), c_in, packed, bias, skip, Y,
+                               reinterpret_cast<short*>(yb_next), c_out, D, H, W, relu, st));
 }
 
 // partial buffer: FP32 tile partials, then (aligned) the BF16 copies of X and dY

@@ -12,7 +12,8 @@ import torch
 from . import lbm
 
 BF16, FP32 = 0, 1
-EXPORTS = ["lbm_nn_packed_words", "lbm_nn_pack", "lbm_nn_conv_work_bytes", "lbm_nn_conv", "lbm_nn_wgrad_partial_words", "lbm_nn_wgrad",
+EXPORTS = ["lbm_nn_packed_words", "lbm_nn_pack", "lbm_nn_conv_work_bytes", "lbm_nn_conv", "lbm_nn_conv_x",
+           "lbm_nn_wgrad_partial_words", "lbm_nn_wgrad",
            "lbm_nn_bias_grad", "lbm_nn_relu_bwd", "lbm_nn_add", "lbm_nn_pool", "lbm_nn_pool_bwd", "lbm_nn_up",
            "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam", "lbm_nn_augment", "lbm_nn_warm_fields",
            "lbm_nn_bias_grad_noalloc"]
@@ -31,6 +32,7 @@ def load():
         lib.lbm_nn_conv_work_bytes.argtypes = [i, i, i, i, i]
         lib.lbm_nn_conv_work_bytes.restype = C.c_size_t
         lib.lbm_nn_conv.argtypes = [vp, i, vp, vp, vp, vp, i, i, i, i, i, i, vp, vp]
+        lib.lbm_nn_conv_x.argtypes = [vp, vp, i, vp, vp, vp, vp, vp, i, i, i, i, i, vp, vp]
         lib.lbm_nn_wgrad_partial_words.argtypes = [i, i, i, i, i]
         lib.lbm_nn_wgrad_partial_words.restype = C.c_size_t
         lib.lbm_nn_wgrad.argtypes = [vp, i, vp, i, i, i, i, vp, vp, i, vp]
@@ -87,6 +89,25 @@ def conv(X: torch.Tensor, packed: torch.Tensor, c_out: int, bias=None, skip=None
     _chk("lbm_nn_conv", lib.lbm_nn_conv(_p(X), c_in, _p(packed), _p(bias), _p(skip), _p(Y), c_out, D, H, W,
                                         int(relu), prec, _p(work), _s()))
     return Y
+
+
+def conv_x(packed: torch.Tensor, c_out: int, c_in: int, dhw, X=None, xb=None, bias=None, skip=None, relu=False,
+           want_y=True, want_yb=False):
+    """BF16 convolution of a chain (lbm_nn_conv_x): input X (FP32) or xb (the
+    BF16 channels-innermost copy a previous call returned); returns (Y or
+    None, yb or None)."""
+    D, H, W = dhw
+    lib = load()
+    dev = (X if X is not None else xb).device
+    Y = torch.empty((c_out, D, H, W), dtype=torch.float32, device=dev) if want_y else None
+    yb = torch.empty(lib.lbm_nn_conv_work_bytes(c_out, D, H, W, BF16), dtype=torch.uint8, device=dev) \
+        if want_yb else None
+    work = None
+    if xb is None:
+        work = torch.empty(lib.lbm_nn_conv_work_bytes(c_in, D, H, W, BF16), dtype=torch.uint8, device=dev)
+    _chk("lbm_nn_conv_x", lib.lbm_nn_conv_x(_p(X), _p(xb), c_in, _p(packed), _p(bias), _p(skip), _p(Y), _p(yb),
+                                            c_out, D, H, W, int(relu), _p(work), _s()))
+    return Y, yb
 
 
 def wgrad(X: torch.Tensor, dY: torch.Tensor, prec=BF16) -> torch.Tensor:

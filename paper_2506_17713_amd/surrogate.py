@@ -96,8 +96,39 @@ class Surrogate:
             return self._add(self._conv(name, x, True, tape), s, tape)
         return nn.conv(x, self.pk[name], self.W[name].shape[0], bias=self.b[name], skip=s, relu=True, prec=self.prec)
 
+    def _forward_chain(self, mask: torch.Tensor) -> torch.Tensor:
+        """Inference in BF16: each convolution hands its successor the BF16
+        channels-innermost copy of its output (lbm_nn_conv_x), and FP32
+        tensors are written only where pooling, upsampling, a skip or the
+        result reads them.  The same operations as forward()."""
+        def cv(name, dhw, X=None, xb=None, skip=None, relu=True, want_y=True, want_yb=True):
+            co, ci = self.W[name].shape[0], self.W[name].shape[1]
+            return nn.conv_x(self.pk[name], co, ci, dhw, X=X, xb=xb, bias=self.b[name], skip=skip, relu=relu,
+                             want_y=want_y, want_yb=want_yb)
+
+        d0 = tuple(mask.shape[1:])
+        d1, d2, d3 = (tuple(v // 2 for v in d0), tuple(v // 4 for v in d0), tuple(v // 8 for v in d0))
+        _, b = cv("enc0a", d0, X=mask, want_y=False)
+        s0, _ = cv("enc0b", d0, xb=b, want_yb=False)
+        _, b = cv("enc1a", d1, X=nn.pool(s0), want_y=False)
+        s1, _ = cv("enc1b", d1, xb=b, want_yb=False)
+        _, b = cv("enc2a", d2, X=nn.pool(s1), want_y=False)
+        s2, _ = cv("enc2b", d2, xb=b, want_yb=False)
+        _, b = cv("bota", d3, X=nn.pool(s2), want_y=False)
+        a, _ = cv("botb", d3, xb=b, want_yb=False)
+        _, b = cv("dec2a", d2, X=nn.up(a), skip=s2, want_y=False)
+        a, _ = cv("dec2b", d2, xb=b, want_yb=False)
+        _, b = cv("dec1a", d1, X=nn.up(a), skip=s1, want_y=False)
+        a, _ = cv("dec1b", d1, xb=b, want_yb=False)
+        _, b = cv("dec0a", d0, X=nn.up(a), skip=s0, want_y=False)
+        _, b = cv("dec0b", d0, xb=b, want_y=False)
+        y, _ = cv("head", d0, xb=b, relu=False, want_yb=False)
+        return y
+
     def forward(self, mask: torch.Tensor, tape=None) -> torch.Tensor:
         """mask: float32 [1, D, H, W] (1 = pore).  D, H, W divisible by 8."""
+        if tape is None and self.prec == nn.BF16:
+            return self._forward_chain(mask)
         c = self._conv
         a = c("enc0a", mask, True, tape)
         s0 = c("enc0b", a, True, tape)

@@ -336,3 +336,24 @@ def test_inference_forward_equals_the_taped_forward(T, ops):
     y0 = model.forward(mask)
     y1 = model.forward(mask, tape=[])
     assert T.equal(y0, y1)
+
+
+@pytest.mark.parametrize("c1,c2,dhw", [(16, 16, (4, 6, 64)), (24, 40, (4, 6, 32)), (8, 16, (6, 4, 10)),
+                                       (16, 4, (3, 4, 70))])
+def test_conv_chain_hands_over_the_bf16_copy(T, ops, c1, c2, dhw):
+    """lbm_nn_conv_x: the BF16 copy written by one convolution is the input the
+    next one would convert from its FP32 output, so a chain gives bitwise the
+    outputs of lbm_nn_conv (LDS rows, 16-row tiles, two 32-row tiles,
+    global-operand rows)."""
+    rng = np.random.default_rng(c1 + c2)
+    X = T.tensor(rng.standard_normal((c1,) + dhw), dtype=T.float32, device="cuda")
+    W1 = T.tensor(rng.standard_normal((c2, c1, 27)) / np.sqrt(c1 * 27), dtype=T.float32, device="cuda")
+    W2 = T.tensor(rng.standard_normal((c1, c2, 27)) / np.sqrt(c2 * 27), dtype=T.float32, device="cuda")
+    b1 = T.tensor(rng.standard_normal(c2), dtype=T.float32, device="cuda")
+    p1, p2 = ops.pack(W1, False, ops.BF16), ops.pack(W2, False, ops.BF16)
+    Y1 = ops.conv(X, p1, c2, bias=b1, relu=True, prec=ops.BF16)
+    Z = ops.conv(Y1, p2, c1, prec=ops.BF16)
+    Y1x, yb = ops.conv_x(p1, c2, c1, dhw, X=X, bias=b1, relu=True, want_y=True, want_yb=True)
+    Zx, _ = ops.conv_x(p2, c1, c2, dhw, xb=yb)
+    assert T.equal(Y1x, Y1)
+    assert T.equal(Zx, Z)
