@@ -99,6 +99,14 @@ int lbm_nn_pool_bwd(const float* dY, int c, int D, int H, int W, float* dX, int 
  * adjoint dX = sum over the 8 children of dY. */
 int lbm_nn_up(const float* X, int c, int D, int H, int W, float* Y, void* stream);
 int lbm_nn_up_bwd(const float* dY, int c, int D, int H, int W, float* dX, void* stream);
+/* The same pooling and upsampling written straight into the BF16 work layout
+ * of a convolution's input ([output positions][c padded to 16], channels
+ * innermost, padding zero; lbm_nn_conv_work_bytes(c, output D, H, W, LBM_NN_BF16)
+ * bytes), for lbm_nn_conv_x(xb = ...) in an inference chain: bitwise the
+ * values that lbm_nn_conv would convert from lbm_nn_pool / lbm_nn_up.
+ * Errors: LBM_ERR_ARG, LBM_ERR_HIP. */
+int lbm_nn_pool_x(const float* X, int c, int D, int H, int W, void* xb, void* stream);
+int lbm_nn_up_x(const float* X, int c, int D, int H, int W, void* xb, void* stream);
 /* Masked mean squared error over c channels: L = sum_{c,p} mask[p] (Y - T)^2 / (c sum_p mask[p]).
  * loss: device double[2 + 512]; loss[0] = L, loss[1] = sum_p mask[p], the rest
  * is scratch.  dY = dL/dY (may be NULL). */

@@ -611,6 +611,61 @@ __global__ void k_up(const float* __restrict__ X, int c, int D, int H, int W, fl
         }
 }
 
+// Pooling and upsampling straight into the BF16 channels-innermost input of a
+// convolution (the work layout: [P][c padded to 16], padding channels zero):
+// the same values as k_pool / k_up followed by the conversion, without the
+// FP32 tensor in between.  Like k_act_pack, a block transposes 64 output
+// positions through LDS (coalesced reads of each channel, one contiguous run
+// of 16-byte words written); MODE 0 pools 2x2x2 of the fine input X [c][D][H][W],
+// MODE 1 copies the coarse parent of X [c][D][H][W] into the 2D x 2H x 2W grid.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_resample_x(const float* __restrict__ X, int c, int D, int H, int W,
+                                                    s16x8* __restrict__ xb) {
+    __shared__ short sh[kPackMaxC][kPackPos + 2];
+    const int Do = MODE == 0 ? D / 2 : 2 * D, Ho = MODE == 0 ? H / 2 : 2 * H, Wo = MODE == 0 ? W / 2 : 2 * W;
+    const int64_t Po = (int64_t)Do * Ho * Wo;
+    const int64_t p0 = (int64_t)blockIdx.x * kPackPos;
+    const int t = threadIdx.x, lp = t % kPackPos;
+    const int64_t po = p0 + lp;
+    const bool ok = po < Po;
+    const int64_t pp = ok ? po : 0;
+    const int x = (int)(pp % Wo), y = (int)((pp / Wo) % Ho), z = (int)(pp / ((int64_t)Wo * Ho));
+    const size_t P = (size_t)D * H * W;
+    const int cip = cin_pad_of(c, LBM_NN_BF16), G = cip / 8;
+    for (int cb = 0; cb < cip; cb += kPackMaxC) {
+        const int nc = cip - cb < kPackMaxC ? cip - cb : kPackMaxC;
+        if (cb > 0) __syncthreads();
+        for (int cl = t / kPackPos; cl < nc; cl += 256 / kPackPos) {
+            const int ch = cb + cl;
+            short v = 0;
+            if (ch < c && ok) {
+                const float* b = X + (size_t)ch * P;
+                if constexpr (MODE == 0) {
+                    float sum = 0.0f;
+                    for (int dz = 0; dz < 2; ++dz)
+                        for (int dy = 0; dy < 2; ++dy)
+                            for (int dx = 0; dx < 2; ++dx)
+                                sum += b[((size_t)(2 * z + dz) * H + 2 * y + dy) * W + 2 * x + dx];
+                    v = f2bf(0.125f * sum);
+                } else {
+                    v = f2bf(b[((size_t)(z / 2) * H + y / 2) * W + x / 2]);
+                }
+            }
+            sh[cl][lp] = v;
+        }
+        __syncthreads();
+        const int Gc = nc / 8;
+        for (int w = t; w < kPackPos * Gc; w += 256) {
+            const int pos = w / Gc, g = w % Gc;
+            if (p0 + pos >= Po) continue;
+            s16x8 v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = sh[8 * g + j][pos];
+            xb[(size_t)(p0 + pos) * G + cb / 8 + g] = v;
+        }
+    }
+}
+
 // coarse index over [c][D][H][W], dY fine
 __global__ void k_up_bwd(const float* __restrict__ dY, int c, int D, int H, int W, float* __restrict__ dX) {
     const int64_t total = (int64_t)c * D * H * W;
@@ -977,6 +1032,22 @@ int lbm_nn_relu_bwd(const float* Y, float* dY, int64_t n, void* stream) {
 
 int lbm_nn_add(float* y, const float* x, int64_t n, void* stream) {
     hipLaunchKernelGGL(k_add, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, y, x, n);
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_pool_x(const float* X, int c, int D, int H, int W, void* xb, void* stream) {
+    if (!X || !xb || c < 1 || D < 2 || H < 2 || W < 2 || ((D | H | W) & 1)) return LBM_ERR_ARG;
+    const int64_t n = (int64_t)(D / 2) * (H / 2) * (W / 2);
+    hipLaunchKernelGGL(k_resample_x<0>, dim3((unsigned)((n + kPackPos - 1) / kPackPos)), dim3(256), 0,
+                       (hipStream_t)stream, X, c, D, H, W, reinterpret_cast<s16x8*>(xb));
+    return ok(hipGetLastError());
+}
+
+int lbm_nn_up_x(const float* X, int c, int D, int H, int W, void* xb, void* stream) {
+    if (!X || !xb || c < 1 || D < 1 || H < 1 || W < 1) return LBM_ERR_ARG;
+    const int64_t n = (int64_t)8 * D * H * W;
+    hipLaunchKernelGGL(k_resample_x<1>, dim3((unsigned)((n + kPackPos - 1) / kPackPos)), dim3(256), 0,
+                       (hipStream_t)stream, X, c, D, H, W, reinterpret_cast<s16x8*>(xb));
     return ok(hipGetLastError());
 }
 

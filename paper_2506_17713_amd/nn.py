@@ -13,6 +13,7 @@ from . import lbm
 
 BF16, FP32 = 0, 1
 EXPORTS = ["lbm_nn_packed_words", "lbm_nn_pack", "lbm_nn_conv_work_bytes", "lbm_nn_conv", "lbm_nn_conv_x",
+           "lbm_nn_pool_x", "lbm_nn_up_x",
            "lbm_nn_wgrad_partial_words", "lbm_nn_wgrad",
            "lbm_nn_bias_grad", "lbm_nn_relu_bwd", "lbm_nn_add", "lbm_nn_pool", "lbm_nn_pool_bwd", "lbm_nn_up",
            "lbm_nn_up_bwd", "lbm_nn_mse", "lbm_nn_adam", "lbm_nn_augment", "lbm_nn_warm_fields",
@@ -33,6 +34,8 @@ def load():
         lib.lbm_nn_conv_work_bytes.restype = C.c_size_t
         lib.lbm_nn_conv.argtypes = [vp, i, vp, vp, vp, vp, i, i, i, i, i, i, vp, vp]
         lib.lbm_nn_conv_x.argtypes = [vp, vp, i, vp, vp, vp, vp, vp, i, i, i, i, i, vp, vp]
+        lib.lbm_nn_pool_x.argtypes = [vp, i, i, i, i, vp, vp]
+        lib.lbm_nn_up_x.argtypes = [vp, i, i, i, i, vp, vp]
         lib.lbm_nn_wgrad_partial_words.argtypes = [i, i, i, i, i]
         lib.lbm_nn_wgrad_partial_words.restype = C.c_size_t
         lib.lbm_nn_wgrad.argtypes = [vp, i, vp, i, i, i, i, vp, vp, i, vp]
@@ -108,6 +111,24 @@ def conv_x(packed: torch.Tensor, c_out: int, c_in: int, dhw, X=None, xb=None, bi
     _chk("lbm_nn_conv_x", lib.lbm_nn_conv_x(_p(X), _p(xb), c_in, _p(packed), _p(bias), _p(skip), _p(Y), _p(yb),
                                             c_out, D, H, W, int(relu), _p(work), _s()))
     return Y, yb
+
+
+def pool_x(X: torch.Tensor) -> torch.Tensor:
+    """2x2x2 average pooling into the BF16 input layout of a convolution (lbm_nn_pool_x)."""
+    c, D, H, W = X.shape
+    lib = load()
+    xb = torch.empty(lib.lbm_nn_conv_work_bytes(c, D // 2, H // 2, W // 2, BF16), dtype=torch.uint8, device=X.device)
+    _chk("lbm_nn_pool_x", lib.lbm_nn_pool_x(_p(X), c, D, H, W, _p(xb), _s()))
+    return xb
+
+
+def up_x(X: torch.Tensor) -> torch.Tensor:
+    """Nearest 2x upsampling into the BF16 input layout of a convolution (lbm_nn_up_x)."""
+    c, D, H, W = X.shape
+    lib = load()
+    xb = torch.empty(lib.lbm_nn_conv_work_bytes(c, 2 * D, 2 * H, 2 * W, BF16), dtype=torch.uint8, device=X.device)
+    _chk("lbm_nn_up_x", lib.lbm_nn_up_x(_p(X), c, D, H, W, _p(xb), _s()))
+    return xb
 
 
 def wgrad(X: torch.Tensor, dY: torch.Tensor, prec=BF16) -> torch.Tensor:

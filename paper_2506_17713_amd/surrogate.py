@@ -98,9 +98,10 @@ class Surrogate:
 
     def _forward_chain(self, mask: torch.Tensor) -> torch.Tensor:
         """Inference in BF16: each convolution hands its successor the BF16
-        channels-innermost copy of its output (lbm_nn_conv_x), and FP32
-        tensors are written only where pooling, upsampling, a skip or the
-        result reads them.  The same operations as forward()."""
+        channels-innermost copy of its output (lbm_nn_conv_x), pooling and
+        upsampling write that layout too, and FP32 tensors are written only
+        where pooling, upsampling, a skip or the result reads them.  The same
+        operations and roundings as forward()."""
         def cv(name, dhw, X=None, xb=None, skip=None, relu=True, want_y=True, want_yb=True):
             co, ci = self.W[name].shape[0], self.W[name].shape[1]
             return nn.conv_x(self.pk[name], co, ci, dhw, X=X, xb=xb, bias=self.b[name], skip=skip, relu=relu,
@@ -110,17 +111,17 @@ class Surrogate:
         d1, d2, d3 = (tuple(v // 2 for v in d0), tuple(v // 4 for v in d0), tuple(v // 8 for v in d0))
         _, b = cv("enc0a", d0, X=mask, want_y=False)
         s0, _ = cv("enc0b", d0, xb=b, want_yb=False)
-        _, b = cv("enc1a", d1, X=nn.pool(s0), want_y=False)
+        _, b = cv("enc1a", d1, xb=nn.pool_x(s0), want_y=False)
         s1, _ = cv("enc1b", d1, xb=b, want_yb=False)
-        _, b = cv("enc2a", d2, X=nn.pool(s1), want_y=False)
+        _, b = cv("enc2a", d2, xb=nn.pool_x(s1), want_y=False)
         s2, _ = cv("enc2b", d2, xb=b, want_yb=False)
-        _, b = cv("bota", d3, X=nn.pool(s2), want_y=False)
+        _, b = cv("bota", d3, xb=nn.pool_x(s2), want_y=False)
         a, _ = cv("botb", d3, xb=b, want_yb=False)
-        _, b = cv("dec2a", d2, X=nn.up(a), skip=s2, want_y=False)
+        _, b = cv("dec2a", d2, xb=nn.up_x(a), skip=s2, want_y=False)
         a, _ = cv("dec2b", d2, xb=b, want_yb=False)
-        _, b = cv("dec1a", d1, X=nn.up(a), skip=s1, want_y=False)
+        _, b = cv("dec1a", d1, xb=nn.up_x(a), skip=s1, want_y=False)
         a, _ = cv("dec1b", d1, xb=b, want_yb=False)
-        _, b = cv("dec0a", d0, X=nn.up(a), skip=s0, want_y=False)
+        _, b = cv("dec0a", d0, xb=nn.up_x(a), skip=s0, want_y=False)
         _, b = cv("dec0b", d0, xb=b, want_y=False)
         y, _ = cv("head", d0, xb=b, relu=False, want_yb=False)
         return y

@@ -357,3 +357,20 @@ def test_conv_chain_hands_over_the_bf16_copy(T, ops, c1, c2, dhw):
     Zx, _ = ops.conv_x(p2, c1, c2, dhw, xb=yb)
     assert T.equal(Y1x, Y1)
     assert T.equal(Zx, Z)
+
+
+@pytest.mark.parametrize("c,dhw", [(16, (4, 6, 64)), (40, (2, 4, 8)), (3, (6, 2, 10))])
+def test_pool_and_up_into_the_bf16_layout(T, ops, c, dhw):
+    """lbm_nn_pool_x / lbm_nn_up_x: bitwise the input a convolution converts
+    from lbm_nn_pool / lbm_nn_up (checked through a convolution of it)."""
+    rng = np.random.default_rng(c)
+    X = T.tensor(rng.standard_normal((c,) + dhw), dtype=T.float32, device="cuda")
+    Wt = T.tensor(rng.standard_normal((8, c, 27)) / np.sqrt(c * 27), dtype=T.float32, device="cuda")
+    pk = ops.pack(Wt, False, ops.BF16)
+    D, H, W = dhw
+    ref = ops.conv(ops.pool(X), pk, 8, prec=ops.BF16)
+    got, _ = ops.conv_x(pk, 8, c, (D // 2, H // 2, W // 2), xb=ops.pool_x(X))
+    assert T.equal(got, ref)
+    ref = ops.conv(ops.up(X), pk, 8, prec=ops.BF16)
+    got, _ = ops.conv_x(pk, 8, c, (2 * D, 2 * H, 2 * W), xb=ops.up_x(X))
+    assert T.equal(got, ref)
