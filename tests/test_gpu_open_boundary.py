@@ -182,3 +182,42 @@ def test_body_force_drainage_with_convective_outlet(oracle_mod, storage):
     out, st, _ = run_pair(oracle_mod, w, mask, rho, 300)
     check_fields(out, storage)
     check_capillary(oracle_mod, w, mask, st, 300)
+
+
+@pytest.mark.parametrize("storage", ["F64", "F32"])
+def test_two_component_reservoirs_d2q9(oracle_mod, storage):
+    # D2Q9 two components (psi = rho), MRT at tau = 1: a non-wetting slug
+    # pushed along the channel by the inlet reservoir's overpressure toward the
+    # wetting outlet reservoir
+    nx, ny = 70, 90
+    mask = channel_2d(nx, ny)
+    g = ((-0.027, 0.57), (0.57, -0.027))
+    y = np.arange(ny)[:, None] * np.ones((ny, nx))
+    front = inputs.tanh_profile(y, 30.0, 3.0, 1.0, 0.0)
+    rho = np.stack([0.03 + 0.97 * front, 0.03 + 0.97 * (1.0 - front)])[:, None]
+    w = Workload("obc_twocomp2d", "D2Q9", (1, ny, nx), nc=2, storage=storage, collision="MRT", tau=(1.0, 1.0),
+                 psi_kind=("DENSITY", "DENSITY"), g=g, wet_mode=("DRHO", "PHI"), wet=(0.1, 1.2),
+                 rho_min=(0.0, 0.0), rho_max=(1.1, 1.1), res_rho=((1.05, 0.03), (0.03, 1.0)), window=(1, ny - 1))
+    _RHO[w.name] = rho
+    out, st, _ = run_pair(oracle_mod, w, mask, rho, 400)
+    check_fields(out, storage)
+    check_capillary(oracle_mod, w, mask, st, 400)
+
+
+def test_convective_outlet_fp32_storage_fp64_arithmetic(oracle_mod):
+    # the outlet's plane kernels on FP32 populations with FP64 arithmetic
+    nx, ny, tau, g = 90, 61, 0.8, 2e-6
+    mask = np.zeros((1, ny, nx), np.uint8)
+    mask[0, :, 0] = 1
+    mask[0, 0, :] = 2
+    mask[0, ny - 1, :] = 4
+    nu, H = (tau - 0.5) / 3.0, nx - 1
+    xs = np.arange(nx) - 0.5 * nx
+    prof = np.where(np.arange(nx) > 0, g / (2.0 * nu) * (H * H / 4.0 - xs ** 2), 0.0)
+    u0 = np.zeros((3, 1, ny, nx))
+    u0[1] = prof
+    w = Workload("obc_conv2d_f32f64", "D2Q9", (1, ny, nx), storage="F32F64", collision="BGK", tau=(tau, tau),
+                 body=(0.0, g, 0.0), res_rho=((1.0, 1.0), (1.0, 1.0)), **IDEAL)
+    out, st, _ = run_pair(oracle_mod, w, mask, np.ones((1, 1, ny, nx)), 400, u0=u0)
+    for c, (er, eu) in out.items():
+        assert er < 1e-4 and eu < 1e-4, (c, er, eu)
