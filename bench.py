@@ -48,6 +48,8 @@ def parse():
                          "every 100)")
     ap.add_argument("--storage", default="F32", choices=["F32", "F64", "F32F64", "F16DEV", "BF16DEV"])
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
+    ap.add_argument("--layout", default="DENSE", choices=["DENSE", "FLUID"],
+                    help="population layout: every node (DENSE) or fluid nodes only (FLUID, porous media)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-table", action="store_true",
@@ -411,6 +413,9 @@ def main():
     storage = args.storage if args.workload != "droplet2d" or args.storage != "F32" else "F64"
     collision = "BGK" if args.workload != "sessile" else args.collision
     w, solid, rho, desc = make_workload(args.workload, n, storage, collision)
+    if args.layout != "DENSE":
+        w = w.with_(layout=args.layout)
+        desc += ", fluid-only layout"
     sol = lbm.Solver(w, solid, rho, device="cuda:0")
     stream = sol.stream
     print(f"# init done {w.shape} {w.storage} {w.collision}", file=sys.stderr, flush=True)
@@ -458,7 +463,9 @@ def main():
                    "fluid_MLUPS": round(w.nc * int((solid == 0).sum()) * args.steps / (ms * 1e-3) / 1e6, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": b_alg, "kernel": "k_step (fused step)"},
+                     "bytes_per_launch": b_alg,
+                     "kernel": "k_step (fused step)" if w.layout == "DENSE" else
+                     "one step = k_fl_rho + k_fl_solid + k_fl_step (fluid-only layout)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

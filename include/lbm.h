@@ -65,6 +65,18 @@ enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16DEV = 2, LBM_STORE_BF1
 enum { LBM_PSI_CS = 0, LBM_PSI_DENSITY = 1 };
 /* Improved virtual density (Eq. 17): rho_s = phi rho_ave or rho_ave - drho. */
 enum { LBM_WET_PHI = 0, LBM_WET_DRHO = 1 };
+/* Population layout in the workspace.
+ * DENSE: every lattice node holds its populations (solid slots unused); the
+ * fused kernel marches tiles of the lattice.
+ * FLUID: only fluid nodes hold populations, listed in lattice order, with a
+ * table of the 18 neighbour indices per fluid node and per solid node next to
+ * fluid (porous media: at porosity 0.35 the dense rows carry about three
+ * times the fluid bytes).  Same method and results as DENSE (pinned by the
+ * parity tests); D3Q19 only, storage F64, F32 or F32_F64, BGK or MRT, no
+ * reservoir or outlet nodes (LBM_ERR_UNSUPPORTED otherwise), and lbm_grad is
+ * LBM_ERR_UNSUPPORTED.  The state of lbm_get_state / lbm_set_state is the
+ * fluid-node populations (lbm_state_bytes). */
+enum { LBM_LAYOUT_DENSE = 0, LBM_LAYOUT_FLUID = 1 };
 
 #define LBM_MAX_COMP 2
 #define LBM_MAX_Q 19
@@ -114,7 +126,8 @@ typedef struct lbm_params {
                                    lbm_stats measures the capillary pressure
                                    and wetting saturation; window[1] <=
                                    window[0]: every plane                      */
-    int32_t reserved2[2];       /* must be zero                                */
+    int32_t layout;             /* LBM_LAYOUT_DENSE or LBM_LAYOUT_FLUID         */
+    int32_t reserved2;          /* must be zero                                */
 } lbm_params;
 
 typedef struct lbm_stats_t {
@@ -144,7 +157,9 @@ typedef struct lbm_handle lbm_handle;
 
 /* Device bytes lbm_init needs in its workspace for these parameters: two
  * population buffers (ping-pong), the per-node neighbour words, the wetting
- * field, moment scratch and reduction partials.  Pure function.
+ * field, moment scratch and reduction partials; with LBM_LAYOUT_FLUID also
+ * the neighbour table and the per-node density and pseudopotential arrays
+ * (sized for the worst case, every node fluid).  Pure function.
  * Errors: LBM_ERR_ARG for an invalid parameter set. */
 int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
 
@@ -171,6 +186,8 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
  *              plane below at time t; its density in the force gather is
  *              that of the node below it (res_rho[1] where that is solid).
  *              Not with 16-bit storage (LBM_ERR_UNSUPPORTED).
+ *              Reservoirs and outlets are not offered with LBM_LAYOUT_FLUID
+ *              (LBM_ERR_UNSUPPORTED).
  *   rho0       host double[n_comp][N], initial density per component.
  *   u0         host double[3][N] initial equilibrium velocity j/rho (x, y, z),
  *              or NULL for rest.  The velocity of Eq. 6 reported by

@@ -9,7 +9,7 @@ HERE = Path(__file__).resolve().parent
 ROOT = HERE.parent
 CSRC = HERE / "csrc"
 OUT = HERE / "_lib" / "liblbm.so"
-SOURCES = ["lbm_api.hip", "lbm_adjoint.hip", "nn.hip"]
+SOURCES = ["lbm_api.hip", "lbm_adjoint.hip", "lbm_fluid.hip", "nn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -534,7 +534,8 @@ int check_req(const lbm_handle* h, const lbm_grad_req* r) {
     if (r->observable == LBM_OBS_DRHO && !r->dL_drho) return LBM_ERR_ARG;
     if (h->p.n_comp != 1) return LBM_ERR_UNSUPPORTED;
     if (h->p.storage != LBM_STORE_F32 && h->p.storage != LBM_STORE_F64) return LBM_ERR_UNSUPPORTED;
-    if (h->p.kappa[0] != 0.0 || h->p.collision == LBM_CLBM || h->has_res) return LBM_ERR_UNSUPPORTED;
+    if (h->p.kappa[0] != 0.0 || h->p.collision == LBM_CLBM || h->has_res || h->p.layout == LBM_LAYOUT_FLUID)
+        return LBM_ERR_UNSUPPORTED;
     return LBM_OK;
 }
 

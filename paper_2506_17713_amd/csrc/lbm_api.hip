@@ -51,7 +51,12 @@ int validate(const lbm_params* p) {
     if (p->check_every < 0) return LBM_ERR_ARG;
     for (int i = 0; i < 4; ++i)
         if (p->reserved[i] != 0) return LBM_ERR_ARG;
-    if (p->reserved2[0] != 0 || p->reserved2[1] != 0) return LBM_ERR_ARG;
+    if (p->reserved2 != 0) return LBM_ERR_ARG;
+    if (p->layout != LBM_LAYOUT_DENSE && p->layout != LBM_LAYOUT_FLUID) return LBM_ERR_ARG;
+    // fluid-only layout: D3Q19, full-precision storage, BGK or MRT
+    if (p->layout == LBM_LAYOUT_FLUID &&
+        (p->lattice != LBM_D3Q19 || is_dev(p->storage) || p->collision == LBM_CLBM))
+        return LBM_ERR_UNSUPPORTED;
     for (int k = 0; k < p->n_comp; ++k) {
         if (!(p->tau[k] > 0.5) || !std::isfinite(p->tau[k])) return LBM_ERR_ARG;
         if (p->psi_kind[k] != LBM_PSI_CS && p->psi_kind[k] != LBM_PSI_DENSITY) return LBM_ERR_ARG;
@@ -98,7 +103,10 @@ Layout layout_of(const lbm_params* p) {
     };
     // lbm_init stages the mask, rho0 and u0 in the second buffer
     const size_t stage = align256(N) + align256(nc * N * rb) + align256(3 * N * rb);
-    const size_t pop = nc * q * N * sb;
+    // the fluid layout's rows have a stride of N rounded up to 64
+    const bool fl = p->layout == LBM_LAYOUT_FLUID;
+    const size_t NT = fl ? (N + 63) / 64 * 64 : N;
+    const size_t pop = nc * q * NT * sb;
     L.fA = take(pop);
     L.fB = take(pop > stage ? pop : stage);
     L.rA = take(is_dev(p->storage) ? nc * N * 4 : 0);
@@ -113,6 +121,12 @@ Layout layout_of(const lbm_params* p) {
     // convective outlet: partial sums of the mean outward velocity
     const size_t plane = (size_t)p->nx * (p->lattice == LBM_D2Q9 ? 1 : p->ny);
     L.conv_part = take(((plane + kConvThreads - 1) / kConvThreads) * 16);
+    L.ftab = take(fl ? (q - 1) * NT * 4 : 0);
+    L.frho = take(fl ? nc * NT * rb : 0);
+    L.fpsi = take(fl ? nc * NT * rb : 0);
+    L.fU = take(fl ? nc * NT * rb : 0);
+    L.fdmap = take(fl ? NT * 4 : 0);
+    L.femap = take(fl ? N * 4 : 0);
     L.total = off;
     return L;
 }
@@ -120,60 +134,6 @@ Layout layout_of(const lbm_params* p) {
 }  // namespace
 
 namespace {
-
-template <class R>
-void fill_args(lbm_handle* h, StepArgs<R>& a, const Buffers* bufs) {
-    const lbm_params& p = h->p;
-    std::memset(&a, 0, sizeof(a));
-    char* ws = h->ws;
-    const bool dev = is_dev(p.storage);
-    a.fin = ws + (h->cur ? h->lay.fB : h->lay.fA);
-    a.fout = ws + (h->cur ? h->lay.fA : h->lay.fB);
-    a.rin = dev ? reinterpret_cast<const float*>(ws + (h->cur ? h->lay.rB : h->lay.rA)) : nullptr;
-    a.rout = dev ? reinterpret_cast<float*>(ws + (h->cur ? h->lay.rA : h->lay.rB)) : nullptr;
-    if (bufs) {
-        a.fin = bufs->fin;
-        a.fout = bufs->fout;
-        a.rin = bufs->rin;
-        a.rout = bufs->rout;
-    }
-    a.nbr = reinterpret_cast<const uint32_t*>(ws + h->lay.nbr);
-    a.wet = reinterpret_cast<const R*>(ws + h->lay.wet);
-    a.NA = h->NA;
-    a.NB = h->NB;
-    a.NC_ = h->NCc;
-    a.N = h->N;
-    a.common_u = p.common_velocity ? 1 : 0;
-    a.wet_uniform = h->wet_uniform ? 1 : 0;
-    a.has_zc = 0;
-    const int q = q_of(p.lattice);
-    for (int k = 0; k < p.n_comp; ++k) {
-        a.psi_cs[k] = p.psi_kind[k] == LBM_PSI_CS;
-        a.wet_drho[k] = p.wet_mode[k] == LBM_WET_DRHO;
-        a.wet_val[k] = (R)p.wet[k];
-        a.omega[k] = (R)(1.0 / p.tau[k]);
-        for (int m = 0; m < q; ++m) {
-            const double nrm = p.lattice == LBM_D2Q9 ? mrt_norm<LAT_D2Q9>(m) : mrt_norm<LAT_D3Q19>(m);
-            a.srate[k][m] = (R)(p.mrt_s[k][m] / nrm);
-        }
-        a.eos_a[k] = (R)p.eos_a[k];
-        a.eos_b[k] = (R)p.eos_b[k];
-        a.eos_RT[k] = (R)(p.eos_R[k] * p.eos_T[k]);
-        a.alpha[k] = (R)p.alpha[k];
-        a.ginv[k] = p.g[k][k] != 0.0 ? (R)(1.0 / p.g[k][k]) : (R)0;
-        a.A[k] = (R)p.A[k];
-        if (p.A[k] != 0.0 && p.psi_kind[k] == LBM_PSI_CS) a.has_zc = 1;
-        for (int kk = 0; kk < p.n_comp; ++kk) a.g[k][kk] = (R)p.g[k][kk];
-        a.rho_min[k] = (R)p.rho_min[k];
-        a.rho_max[k] = (R)p.rho_max[k];
-        a.kq[k] = (R)(p.kappa[k] * p.g[k][k]);
-        for (int r = 0; r < 2; ++r) {
-            a.res_rho[r][k] = (R)p.res_rho[r][k];
-            a.res_abb[r][k] = (R)h->res_active[r][k];
-        }
-    }
-    for (int d = 0; d < 3; ++d) a.body[d] = (R)p.body_accel[d];
-}
 
 // Tile height of a step kernel.  For BGK with one FP32 component or two
 // 16-bit ones, 64 x 8 tiles at 2 waves per SIMD beat 64 x 4 at 3: a taller
@@ -340,6 +300,10 @@ hipError_t run_conv(lbm_handle* h) {
 
 hipError_t run_kernel(lbm_handle* h, bool mom, int comp = -1, void* rho = nullptr, void* u = nullptr,
                       const Buffers* bufs = nullptr) {
+    if (h->p.layout == LBM_LAYOUT_FLUID) {
+        if (bufs) return hipErrorInvalidValue;  // explicit buffers: the adjoint only, dense layout
+        return mom ? fluid_moments(h, comp, rho, u) : fluid_step(h);
+    }
     const bool d2 = h->p.lattice == LBM_D2Q9;
     if (d2) {
         if (h->p.n_comp == 1) return dispatch_store<LAT_D2Q9, 1>(h, mom, comp, rho, u, bufs);
@@ -597,6 +561,7 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
             return LBM_ERR_ARG;
         if (is_dev(p->storage)) return LBM_ERR_UNSUPPORTED;
     }
+    if (has_res && p->layout == LBM_LAYOUT_FLUID) return LBM_ERR_UNSUPPORTED;
     size_t n_solid = 0;
     for (size_t n = 0; n < N; ++n) {
         if (mask[n]) {
@@ -628,6 +593,7 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     h->wet_uniform = wet == nullptr;
     h->has_res = has_res;
     h->conv_plane = conv_plane;
+    h->n_fl = h->n_ext = h->fl_T = 0;
     std::memcpy(h->res_active, p->res_rho, sizeof(h->res_active));
     h->mostly_fluid = n_solid * 10 < N;
     // LBM_CHUNK (environment, tuning only): planes per workgroup along the
@@ -678,7 +644,14 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
                                (const uint8_t*)d_mask, (uint32_t*)(h->ws + lay.nbr), h->NA, h->NB, h->NCc);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) {
+    if (e == hipSuccess && p->layout == LBM_LAYOUT_FLUID) {
+        rc = fluid_build(h);
+        if (rc != LBM_OK) {
+            delete h;
+            return rc;
+        }
+        e = fluid_init(h, d_rho, u0 ? d_u : nullptr);
+    } else if (e == hipSuccess) {
         const void* du = u0 ? d_u : nullptr;
         if (p->lattice == LBM_D2Q9)
             e = nc == 1 ? init_store<LAT_D2Q9, 1>(h, d_rho, du) : init_store<LAT_D2Q9, 2>(h, d_rho, du);
@@ -775,9 +748,14 @@ int lbm_set_reservoir(lbm_handle* h, int r, const double* rho) {
     return LBM_OK;
 }
 
+// Nodes per population row of the state: the lattice, or the fluid-layout stride.
+static size_t state_rows(const lbm_handle* h) {
+    return h->p.layout == LBM_LAYOUT_FLUID ? (size_t)h->fl_T : (size_t)h->N;
+}
+
 int lbm_state_bytes(const lbm_handle* h, size_t* bytes_out) {
     if (!h || !bytes_out) return LBM_ERR_ARG;
-    const size_t N = h->N;
+    const size_t N = state_rows(h);
     *bytes_out = (size_t)h->p.n_comp * q_of(h->p.lattice) * N * store_bytes(h->p.storage) +
                  (is_dev(h->p.storage) ? (size_t)h->p.n_comp * N * 4 : 0);
     return LBM_OK;
@@ -785,7 +763,7 @@ int lbm_state_bytes(const lbm_handle* h, size_t* bytes_out) {
 
 int lbm_get_state(lbm_handle* h, void* dev_dst) {
     if (!h || !dev_dst) return LBM_ERR_ARG;
-    const size_t N = h->N;
+    const size_t N = state_rows(h);
     const size_t fb = (size_t)h->p.n_comp * q_of(h->p.lattice) * N * store_bytes(h->p.storage);
     hipError_t e = hipMemcpyAsync(dev_dst, h->ws + (h->cur ? h->lay.fB : h->lay.fA), fb,
                                   hipMemcpyDeviceToDevice, h->stream);
@@ -797,7 +775,7 @@ int lbm_get_state(lbm_handle* h, void* dev_dst) {
 
 int lbm_set_state(lbm_handle* h, const void* dev_src) {
     if (!h || !dev_src) return LBM_ERR_ARG;
-    const size_t N = h->N;
+    const size_t N = state_rows(h);
     const size_t fb = (size_t)h->p.n_comp * q_of(h->p.lattice) * N * store_bytes(h->p.storage);
     hipError_t e = hipMemcpyAsync(h->ws + (h->cur ? h->lay.fB : h->lay.fA), dev_src, fb,
                                   hipMemcpyDeviceToDevice, h->stream);
@@ -817,7 +795,9 @@ int lbm_reset(lbm_handle* h, const void* rho0_dev, const void* u0_dev) {
     const Layout& lay = h->lay;
     hipError_t e = hipMemsetAsync(h->ws + lay.dstats, 0, kStatSlots * 8 + 8, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + lay.fA, 0, lay.fB - lay.fA, h->stream);
-    if (e == hipSuccess) {
+    if (e == hipSuccess && h->p.layout == LBM_LAYOUT_FLUID) {
+        e = fluid_init(h, rho0_dev, u0_dev);
+    } else if (e == hipSuccess) {
         const int nc = h->p.n_comp;
         if (h->p.lattice == LBM_D2Q9)
             e = nc == 1 ? init_store<LAT_D2Q9, 1>(h, rho0_dev, u0_dev) : init_store<LAT_D2Q9, 2>(h, rho0_dev, u0_dev);

@@ -1,0 +1,614 @@
+// Fluid-only layout (LBM_LAYOUT_FLUID): the fused Shan-Chen step of the
+// dense kernels (streaming with halfway bounce-back, Eq. 1-2; moments, Eq. 4
+// and 10; virtual densities at solids, Eq. 17; pseudopotential, Eq. 12;
+// interaction force, Eq. 11 and 13; BGK or MRT collision with the
+// exact-difference forcing, Eq. 3 and 5) over a list of the fluid nodes.
+//
+// In a sphere pack at porosity 0.35-0.4 a dense row of 64 nodes holds about
+// 25 fluid nodes, and the dense kernel reads whole cache lines of them: about
+// 2.5 times the fluid bytes, and three pulls per node (own ring pull, halo
+// pulls of the neighbouring tiles, re-pull at the collision).  Here only the
+// fluid nodes hold populations, in lattice order, and each step is two
+// passes over them:
+//   k_fl_rho    pull, density and psi of every fluid node;
+//   k_fl_solid  virtual density and psi of every solid node next to fluid;
+//   k_fl_step   pull again, gather psi of the 18 neighbours, force,
+//               collision, store.
+// Both pulls read the neighbour table (ids of x - e_i), one 4-byte index per
+// direction and node; the gather reads psi through the same ids.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+using namespace lbmi;
+
+namespace {
+
+constexpr int kFlThreads = 256;
+using L = Lat<LAT_D3Q19>;
+constexpr int Q = L::Q;
+constexpr int NP = (Q - 1) / 2;
+
+// Addresses of the fluid-layout arrays (besides StepArgs).
+template <class R>
+struct FlArgs {
+    const int32_t* tab;   // [Q-1][T]: id of x - e_i (ids >= n_fl: solid; -1: solid without fluid neighbour)
+    const int32_t* dmap;  // [T]: lattice index of id
+    const int32_t* emap;  // [N]: id of lattice node, -1 for a solid without fluid neighbour
+    R* rho;               // [NC][T]: density of the fluid ids
+    R* psi;               // [NC][T]: psi of every id
+    R* U;                 // [NC][T]: U of every id (Zhang-Chen term only)
+    int n_fl, n_ext, T;
+};
+
+// Workgroup -> block of ids: consecutive blocks on one XCD (the hardware
+// deals workgroups round-robin over 8 XCDs), so that the neighbour planes a
+// block pulls from were just read by the same L2.
+__device__ __forceinline__ int xcd_block() {
+    const int nblk = gridDim.x, bid = blockIdx.x;
+    const int per = nblk >> 3, rem = nblk & 7, xcd = bid & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + (bid >> 3);
+}
+
+// Neighbour ids src[i] of x - e_i (src[0] = the node itself) and the pull
+// f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) where x - e_i is solid.
+template <int NC, int ST>
+__device__ __forceinline__ void fl_pull(const StepArgs<typename Store<ST>::R>& P,
+                                        const FlArgs<typename Store<ST>::R>& A, int e, int32_t (&src)[Q],
+                                        typename Store<ST>::R (&f)[NC][Q]) {
+    using S = typename Store<ST>::S;
+    using R = typename Store<ST>::R;
+    const size_t T = (size_t)A.T;
+    const S* fin = reinterpret_cast<const S*>(P.fin);
+    src[0] = e;
+    sfor<Q - 1>([&](auto I) {
+        constexpr int i = decltype(I)::value + 1;
+        src[i] = A.tab[(size_t)(i - 1) * T + e];
+    });
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        // a solid source (id >= n_fl, or -1) bounces back the node's own opposite population
+        const bool bb = i != 0 && (uint32_t)src[i] >= (uint32_t)A.n_fl;
+        const size_t off = bb ? (size_t)opp(i) * T + e : (size_t)i * T + (uint32_t)src[i];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) f[k][i] = (R)fin[(size_t)k * Q * T + off];
+    });
+}
+
+// rho^k = sum_i f_i, summed as in the dense kernels (rest, then pairs)
+template <int NC, class R>
+__device__ __forceinline__ R fl_rho_sum(const R (&f)[NC][Q], int k) {
+    R r = f[k][0];
+    sfor<NP>([&](auto PI) {
+        constexpr int i = 2 * decltype(PI)::value + 1;
+        r += f[k][i] + f[k][i + 1];
+    });
+    return r;
+}
+
+// Density and momentum (Eq. 4) and the total force (Eq. 11, 13 plus the
+// body force) of fluid id e from its pulled populations and the psi (and U)
+// of its neighbours, in the operation order of the dense kernels.
+template <int NC, class R>
+__device__ __forceinline__ void fl_moments_force(const StepArgs<R>& P, const FlArgs<R>& A, int e,
+                                                 const int32_t (&src)[Q], const R (&f)[NC][Q], R (&rho)[NC],
+                                                 R (&j)[NC][3], R (&F)[NC][3]) {
+    const size_t T = (size_t)A.T;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        R r = f[k][0], dl[NP];
+        sfor<NP>([&](auto PI) {
+            constexpr int p = decltype(PI)::value;
+            constexpr int i = 2 * p + 1;
+            r += f[k][i] + f[k][i + 1];
+            dl[p] = f[k][i] - f[k][i + 1];
+        });
+        rho[k] = r;
+        pair_sums<LAT_D3Q19, -1>(dl, j[k]);
+    }
+    // D^kk = sum_i G_i psi^kk(x + e_i) e_i as differences across opposite
+    // neighbours; x + e_i = x - e_opp(i) is src[i + 1] for odd i
+    constexpr R G0 = (R)(3.0 * L::w(1));
+    constexpr R G1 = (R)(3.0 * L::w(Q - 1));
+    auto gather = [&](const R* arr, int kk, R(&out)[3]) {
+        R dv[NP];
+        sfor<NP>([&](auto PI) {
+            constexpr int i = 2 * decltype(PI)::value + 1;
+            dv[decltype(PI)::value] = arr[(size_t)kk * T + (uint32_t)src[i + 1]] - arr[(size_t)kk * T + (uint32_t)src[i]];
+        });
+        R s0[3], s1[3];
+        pair_sums<LAT_D3Q19, 0>(dv, s0);
+        pair_sums<LAT_D3Q19, 1>(dv, s1);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) out[d] = G0 * s0[d] + G1 * s1[d];
+    };
+    R Dps[NC][3];
+#pragma unroll
+    for (int kk = 0; kk < NC; ++kk) gather(A.psi, kk, Dps[kk]);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const R psik = A.psi[(size_t)k * T + e];
+        const R Bk = (R)1 - P.A[k];
+        R sv[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            R t = P.g[k][0] * Dps[0][d];
+#pragma unroll
+            for (int kk = 1; kk < NC; ++kk) t += P.g[k][kk] * Dps[kk][d];
+            sv[d] = t;
+        }
+        const R cpsi = -Bk * psik;
+        F[k][0] = cpsi * sv[0] + rho[k] * P.body[0];
+        F[k][1] = cpsi * sv[1] + rho[k] * P.body[1];
+        F[k][2] = cpsi * sv[2] + rho[k] * P.body[2];
+        if (P.has_zc) {
+            R zu[3];
+            gather(A.U, k, zu);
+            F[k][0] -= P.A[k] * zu[0];
+            F[k][1] -= P.A[k] * zu[1];
+            F[k][2] -= P.A[k] * zu[2];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: density and psi of the fluid ids.
+// ---------------------------------------------------------------------------
+template <int NC, int ST>
+__global__ void __launch_bounds__(kFlThreads)
+    k_fl_rho(StepArgs<typename Store<ST>::R> P, FlArgs<typename Store<ST>::R> A) {
+    using R = typename Store<ST>::R;
+    const int e = xcd_block() * kFlThreads + threadIdx.x;
+    if (e >= A.n_fl) return;
+    int32_t src[Q];
+    R f[NC][Q];
+    fl_pull<NC, ST>(P, A, e, src, f);
+    const size_t T = (size_t)A.T;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const R r = fl_rho_sum<NC>(f, k);
+        R ps, u;
+        psi_of(P, k, r, ps, u);
+        A.rho[k * T + e] = r;
+        A.psi[k * T + e] = ps;
+        if (P.has_zc) A.U[k * T + e] = u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: virtual density (Eq. 17) and psi of the solid ids: the
+// weight-averaged density of the fluid neighbours x + e_i (in direction
+// order), then phi rho_ave or rho_ave - drho, limited to [rho_min, rho_max].
+// ---------------------------------------------------------------------------
+template <int NC, class R>
+__global__ void __launch_bounds__(kFlThreads) k_fl_solid(StepArgs<R> P, FlArgs<R> A) {
+    const int s = A.n_fl + blockIdx.x * kFlThreads + threadIdx.x;
+    if (s >= A.n_ext) return;
+    const size_t T = (size_t)A.T;
+    R num[NC], den = 0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) num[k] = 0;
+    sfor<Q - 1>([&](auto I) {
+        constexpr int i = decltype(I)::value + 1;
+        const int32_t nb = A.tab[(size_t)(opp(i) - 1) * T + s];  // x + e_i
+        if ((uint32_t)nb < (uint32_t)A.n_fl) {
+            den += (R)L::w(i);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) num[k] += (R)L::w(i) * A.rho[(size_t)k * T + nb];
+        }
+    });
+    const int n = A.dmap[s];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        R ps = 0, u = 0;
+        if (den > (R)0) {
+            const R rave = num[k] / den;
+            const R prm = P.wet_uniform ? P.wet_val[k] : P.wet[(size_t)k * P.N + n];
+            R rsv = P.wet_drho[k] ? rave - prm : prm * rave;
+            rsv = rsv < P.rho_min[k] ? P.rho_min[k] : rsv;
+            rsv = rsv > P.rho_max[k] ? P.rho_max[k] : rsv;
+            psi_of(P, k, rsv, ps, u);
+        }
+        A.psi[k * T + s] = ps;
+        if (P.has_zc) A.U[k * T + s] = u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3: the fused collision of the fluid ids.  The node collision restates
+// that of the dense kernel for D3Q19 (BGK and the MRT pair form), in the same
+// operations and order; the dense kernel keeps its own inline copy, whose
+// register allocation its tile pipeline is tuned to.
+// ---------------------------------------------------------------------------
+template <int NC, int ST, int COLL>
+__global__ void __launch_bounds__(kFlThreads)
+    k_fl_step(StepArgs<typename Store<ST>::R> P, FlArgs<typename Store<ST>::R> A) {
+    using S = typename Store<ST>::S;
+    using R = typename Store<ST>::R;
+    const int e = xcd_block() * kFlThreads + threadIdx.x;
+    if (e >= A.n_fl) return;
+    const size_t T = (size_t)A.T;
+    int32_t src[Q];
+    R f[NC][Q];
+    fl_pull<NC, ST>(P, A, e, src, f);
+    R rho[NC], j[NC][3], F[NC][3];
+    fl_moments_force<NC>(P, A, e, src, f, rho, j, F);
+
+    // equilibrium velocity: j / rho, or the common u' of two components
+    R ueq[NC][3];
+    if (NC > 1 && P.common_u) {
+        R nx_ = 0, ny_ = 0, nz_ = 0, d = 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            nx_ += j[k][0] * P.omega[k];
+            ny_ += j[k][1] * P.omega[k];
+            nz_ += j[k][2] * P.omega[k];
+            d += rho[k] * P.omega[k];
+        }
+        const R inv = (R)1 / d;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            ueq[k][0] = nx_ * inv;
+            ueq[k][1] = ny_ * inv;
+            ueq[k][2] = nz_ * inv;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const R inv = (R)1 / rho[k];
+            ueq[k][0] = j[k][0] * inv;
+            ueq[k][1] = j[k][1] * inv;
+            ueq[k][2] = j[k][2] * inv;
+        }
+    }
+    S* out = reinterpret_cast<S*>(P.fout);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const R r = rho[k];
+        const R invr = (R)1 / r;
+        const R ux = ueq[k][0], uy = ueq[k][1], uz = ueq[k][2];
+        // du = F / rho; f^eq and the forcing term dF = f^eq(u + du) - f^eq(u)
+        // split into the even part shared by opposite directions and the
+        // odd part, each as w rho times a velocity bracket
+        const R dx = F[k][0] * invr, dy = F[k][1] * invr, dz = F[k][2] * invr;
+        const R usq = (R)1.5 * (ux * ux + uy * uy + uz * uz);
+        const R dsq = (R)1.5 * ((R)2 * (ux * dx + uy * dy + uz * dz) + dx * dx + dy * dy + dz * dz);
+        const R wr0 = (R)L::w(0) * r;
+        const R wrA = (R)L::w(1) * r;
+        const R wrB = (R)L::w(Q - 1) * r;
+        R fo[Q];
+        if constexpr (COLL == COLL_BGK) {
+            const R om = P.omega[k], om1 = (R)1 - om;
+            const R woA = om * wrA, woB = om * wrB;
+            sfor<NP>([&](auto PI) {
+                constexpr int p = decltype(PI)::value;
+                constexpr int i = 2 * p + 1;
+                const R wr = pair_in<LAT_D3Q19>(p, 0) ? wrA : wrB;
+                const R wo = pair_in<LAT_D3Q19>(p, 0) ? woA : woB;
+                const R eu = dot_e<L::ex[i], L::ey[i], L::ez[i]>(ux, uy, uz);
+                const R ed = dot_e<L::ex[i], L::ey[i], L::ez[i]>(dx, dy, dz);
+                const R se = om * ((R)4.5 * (eu * eu) - usq) + ((R)4.5 * ed * ((R)2 * eu + ed) - dsq);
+                const R so = (R)3 * (om * eu + ed);
+                fo[i] = om1 * f[k][i] + (wo + wr * (se + so));
+                fo[i + 1] = om1 * f[k][i + 1] + (wo + wr * (se - so));
+            });
+        } else {
+            static_assert(COLL == COLL_MRT, "fluid layout: BGK or MRT");
+            // f* = f - M^-1 S M (f - f^eq) + dF in the pair form
+            R dp[NP], dm[NP];
+            sfor<NP>([&](auto PI) {
+                constexpr int p = decltype(PI)::value;
+                constexpr int i = 2 * p + 1;
+                const R wr = pair_in<LAT_D3Q19>(p, 0) ? wrA : wrB;
+                const R eu = dot_e<L::ex[i], L::ey[i], L::ez[i]>(ux, uy, uz);
+                const R qs = wr + wr * ((R)4.5 * (eu * eu) - usq);
+                const R qa = wr * ((R)3 * eu);
+                dp[p] = (f[k][i] + f[k][i + 1]) - (R)2 * qs;
+                dm[p] = (f[k][i] - f[k][i + 1]) - (R)2 * qa;
+            });
+            const R d0 = f[k][0] - (wr0 - wr0 * usq);
+            R sr[19], E[NP], O[NP];
+#pragma unroll
+            for (int mm = 0; mm < 19; ++mm) sr[mm] = P.srate[k][mm];
+            mrt_pairs_d3q19<R, (NC > 1)>(dp, dm, d0, sr, E, O);
+            sfor<NP>([&](auto PI) {
+                constexpr int p = decltype(PI)::value;
+                constexpr int i = 2 * p + 1;
+                const R wr = pair_in<LAT_D3Q19>(p, 0) ? wrA : wrB;
+                const R eu = dot_e<L::ex[i], L::ey[i], L::ez[i]>(ux, uy, uz);
+                const R ed = dot_e<L::ex[i], L::ey[i], L::ez[i]>(dx, dy, dz);
+                const R fs = wr * ((R)4.5 * ed * ((R)2 * eu + ed) - dsq);
+                const R fa = wr * ((R)3 * ed);
+                const R as = fs - E[p], aa = fa - O[p];
+                fo[i] = f[k][i] + (as + aa);
+                fo[i + 1] = f[k][i + 1] + (as - aa);
+            });
+        }
+        // the rest population takes the remainder, so that sum_i f*_i = rho
+        R m = 0;
+        sfor<NP>([&](auto PI) {
+            constexpr int i = 2 * decltype(PI)::value + 1;
+            m += fo[i] + fo[i + 1];
+        });
+        fo[0] = r - m;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) __builtin_nontemporal_store((S)fo[i], out + ((size_t)(k * Q + i)) * T + e);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Moments in lattice order (Eq. 6, u = (j + F/2) / rho, per component or for
+// the mixture), zero at solid nodes: one thread per lattice node.
+// ---------------------------------------------------------------------------
+template <int NC, int ST>
+__global__ void __launch_bounds__(kFlThreads)
+    k_fl_mom(StepArgs<typename Store<ST>::R> P, FlArgs<typename Store<ST>::R> A) {
+    using R = typename Store<ST>::R;
+    const int n = blockIdx.x * kFlThreads + threadIdx.x;
+    const size_t N = (size_t)P.N;
+    if (n >= P.N) return;
+    const int e = A.emap[n];
+    if ((uint32_t)e >= (uint32_t)A.n_fl) {
+        if (P.mom_rho) P.mom_rho[n] = 0;
+        if (P.mom_u) {
+            P.mom_u[n] = 0;
+            P.mom_u[N + n] = 0;
+            P.mom_u[2 * N + n] = 0;
+        }
+        return;
+    }
+    int32_t src[Q];
+    R f[NC][Q];
+    fl_pull<NC, ST>(P, A, e, src, f);
+    R rho[NC], j[NC][3], F[NC][3];
+    fl_moments_force<NC>(P, A, e, src, f, rho, j, F);
+    R rr = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        if (P.mom_comp < 0 || P.mom_comp == k) {
+            rr += rho[k];
+            mx += j[k][0] + (R)0.5 * F[k][0];
+            my += j[k][1] + (R)0.5 * F[k][1];
+            mz += j[k][2] + (R)0.5 * F[k][2];
+        }
+    }
+    if (P.mom_rho) P.mom_rho[n] = rr;
+    if (P.mom_u) {
+        const R inv = (R)1 / rr;
+        P.mom_u[n] = mx * inv;
+        P.mom_u[N + n] = my * inv;
+        P.mom_u[2 * N + n] = mz * inv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Populations whose first pull gives f^eq(rho0, u0) at every fluid node
+// (the dense initialisation restricted to fluid ids): f*_i(y) = f^eq_i(y +
+// e_i) where y + e_i is fluid, else the population bounced back into y,
+// f^eq_opp(i)(y).
+// ---------------------------------------------------------------------------
+template <int NC, int ST>
+__global__ void __launch_bounds__(kFlThreads)
+    k_fl_init(const typename Store<ST>::R* __restrict__ rho0, const typename Store<ST>::R* __restrict__ u0,
+              FlArgs<typename Store<ST>::R> A, void* fout, int N) {
+    using S = typename Store<ST>::S;
+    using R = typename Store<ST>::R;
+    const int e = blockIdx.x * kFlThreads + threadIdx.x;
+    if (e >= A.n_fl) return;
+    const size_t T = (size_t)A.T;
+    S* out = reinterpret_cast<S*>(fout);
+    const int n = A.dmap[e];
+    auto feq = [&](int k, int m, int ex, int ey, int ez, double wi) -> R {
+        const R r = rho0[(size_t)k * N + m];
+        const R ux = u0 ? u0[m] : (R)0, uy = u0 ? u0[(size_t)N + m] : (R)0, uz = u0 ? u0[2 * (size_t)N + m] : (R)0;
+        const R eu = ex * ux + ey * uy + ez * uz;
+        return (R)wi * r * ((R)1 + (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * (ux * ux + uy * uy + uz * uz));
+    };
+    for (int k = 0; k < NC; ++k) {
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int o = opp(i);
+            R v;
+            if (i == 0) {
+                v = feq(k, n, 0, 0, 0, L::w(0));
+            } else {
+                const int32_t nb = A.tab[(size_t)(o - 1) * T + e];  // y + e_i
+                if ((uint32_t)nb < (uint32_t)A.n_fl)
+                    v = feq(k, A.dmap[nb], L::ex[i], L::ey[i], L::ez[i], L::w(i));
+                else
+                    v = feq(k, n, L::ex[o], L::ey[o], L::ez[o], L::w(o));
+            }
+            out[(size_t)(k * Q + i) * T + e] = (S)v;
+        });
+    }
+}
+
+// Neighbour table: tab[i-1][id] = emap[x_id - e_i] (periodic wrap).
+__global__ void __launch_bounds__(kFlThreads)
+    k_fl_table(const int32_t* __restrict__ emap, const int32_t* __restrict__ dmap, int32_t* __restrict__ tab,
+               int n_ext, int T, int NA, int NB, int NCc) {
+    const int e = blockIdx.x * kFlThreads + threadIdx.x;
+    if (e >= n_ext) return;
+    const int n = dmap[e];
+    const int a = n % NA, b = (n / NA) % NB, c = n / (NA * NB);
+    sfor<Q - 1>([&](auto I) {
+        constexpr int i = decltype(I)::value + 1;
+        const int aa = wrap_any(a - L::ea(i), NA);
+        const int bb = wrap_any(b - L::eb(i), NB);
+        const int cc = wrap_any(c - L::ec(i), NCc);
+        tab[(size_t)(i - 1) * T + e] = emap[((size_t)cc * NB + bb) * NA + aa];
+    });
+}
+
+template <class R>
+FlArgs<R> fl_args(lbm_handle* h) {
+    FlArgs<R> A;
+    char* ws = h->ws;
+    A.tab = reinterpret_cast<const int32_t*>(ws + h->lay.ftab);
+    A.dmap = reinterpret_cast<const int32_t*>(ws + h->lay.fdmap);
+    A.emap = reinterpret_cast<const int32_t*>(ws + h->lay.femap);
+    A.rho = reinterpret_cast<R*>(ws + h->lay.frho);
+    A.psi = reinterpret_cast<R*>(ws + h->lay.fpsi);
+    A.U = reinterpret_cast<R*>(ws + h->lay.fU);
+    A.n_fl = h->n_fl;
+    A.n_ext = h->n_ext;
+    A.T = h->fl_T;
+    return A;
+}
+
+inline int blocks(int n) { return (n + kFlThreads - 1) / kFlThreads; }
+
+// psi of every listed node (passes 1 and 2)
+template <int NC, int ST>
+hipError_t launch_psi(lbm_handle* h, const StepArgs<typename Store<ST>::R>& a,
+                      const FlArgs<typename Store<ST>::R>& A) {
+    using R = typename Store<ST>::R;
+    if (h->n_fl > 0)
+        hipLaunchKernelGGL((k_fl_rho<NC, ST>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream, a, A);
+    if (h->n_ext > h->n_fl)
+        hipLaunchKernelGGL((k_fl_solid<NC, R>), dim3(blocks(h->n_ext - h->n_fl)), dim3(kFlThreads), 0, h->stream,
+                           a, A);
+    return hipGetLastError();
+}
+
+template <int NC, int ST>
+hipError_t step_store(lbm_handle* h) {
+    using R = typename Store<ST>::R;
+    StepArgs<R> a;
+    fill_args(h, a, nullptr);
+    const FlArgs<R> A = fl_args<R>(h);
+    hipError_t e = launch_psi<NC, ST>(h, a, A);
+    if (e != hipSuccess || h->n_fl == 0) return e;
+    if (h->p.collision == LBM_MRT)
+        hipLaunchKernelGGL((k_fl_step<NC, ST, COLL_MRT>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream, a,
+                           A);
+    else
+        hipLaunchKernelGGL((k_fl_step<NC, ST, COLL_BGK>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream, a,
+                           A);
+    return hipGetLastError();
+}
+
+template <int NC, int ST>
+hipError_t mom_store(lbm_handle* h, int comp, void* rho, void* u) {
+    using R = typename Store<ST>::R;
+    StepArgs<R> a;
+    fill_args(h, a, nullptr);
+    a.mom_comp = comp;
+    a.mom_rho = reinterpret_cast<R*>(rho);
+    a.mom_u = reinterpret_cast<R*>(u);
+    const FlArgs<R> A = fl_args<R>(h);
+    hipError_t e = launch_psi<NC, ST>(h, a, A);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fl_mom<NC, ST>), dim3(blocks(h->N)), dim3(kFlThreads), 0, h->stream, a, A);
+    return hipGetLastError();
+}
+
+template <int NC, int ST>
+hipError_t init_store(lbm_handle* h, const void* rho0, const void* u0) {
+    using R = typename Store<ST>::R;
+    if (h->n_fl == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fl_init<NC, ST>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream,
+                       (const R*)rho0, (const R*)u0, fl_args<R>(h), h->ws + h->lay.fA, h->N);
+    return hipGetLastError();
+}
+
+// Dispatch over components and storage (F64, F32, F32 with FP64 arithmetic).
+template <template <int, int> class Fn, class... Args>
+hipError_t dispatch(lbm_handle* h, Args... args) {
+    const int nc = h->p.n_comp;
+    switch (h->p.storage) {
+        case LBM_STORE_F64:
+            return nc == 1 ? Fn<1, ST_F64>::run(h, args...) : Fn<2, ST_F64>::run(h, args...);
+        case LBM_STORE_F32:
+            return nc == 1 ? Fn<1, ST_F32>::run(h, args...) : Fn<2, ST_F32>::run(h, args...);
+        case LBM_STORE_F32_F64:
+            return nc == 1 ? Fn<1, ST_F32D>::run(h, args...) : Fn<2, ST_F32D>::run(h, args...);
+        default: return hipErrorInvalidValue;  // rejected at lbm_init
+    }
+}
+template <int NC, int ST>
+struct StepFn {
+    static hipError_t run(lbm_handle* h) { return step_store<NC, ST>(h); }
+};
+template <int NC, int ST>
+struct MomFn {
+    static hipError_t run(lbm_handle* h, int comp, void* rho, void* u) { return mom_store<NC, ST>(h, comp, rho, u); }
+};
+template <int NC, int ST>
+struct InitFn {
+    static hipError_t run(lbm_handle* h, const void* rho0, const void* u0) { return init_store<NC, ST>(h, rho0, u0); }
+};
+
+}  // namespace
+
+int lbmi::fluid_build(lbm_handle* h) {
+    const size_t N = (size_t)h->N;
+    // which solid nodes have a fluid neighbour: from the neighbour words
+    // (bit 0: the node is solid; bit i: x - e_i is solid)
+    std::vector<uint32_t> word;
+    std::vector<int32_t> emap, dmap;
+    try {
+        word.resize(N);
+        emap.assign(N, -1);
+        dmap.reserve(N);
+    } catch (...) {
+        return LBM_ERR_OOM;
+    }
+    if (hipMemcpyAsync(word.data(), h->ws + h->lay.nbr, N * 4, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return LBM_ERR_HIP;
+    constexpr uint32_t ALLNB = ((1u << Q) - 1u) & ~1u;
+    for (size_t n = 0; n < N; ++n)
+        if (!(word[n] & 1u)) {
+            emap[n] = (int32_t)dmap.size();
+            dmap.push_back((int32_t)n);
+        }
+    h->n_fl = (int)dmap.size();
+    for (size_t n = 0; n < N; ++n)
+        if ((word[n] & 1u) && (word[n] & ALLNB) != ALLNB) {
+            emap[n] = (int32_t)dmap.size();
+            dmap.push_back((int32_t)n);
+        }
+    h->n_ext = (int)dmap.size();
+    h->fl_T = (int)((N + 63) / 64 * 64);
+    // every neighbour of a fluid node is listed (fluid, or solid next to
+    // fluid), so the pulls and gathers of the step index only listed ids
+    const int NA = h->NA, NB = h->NB, NCc = h->NCc;
+    for (int e = 0; e < h->n_fl; ++e) {
+        const int n = dmap[e];
+        const int a = n % NA, b = (n / NA) % NB, c = n / (NA * NB);
+        for (int i = 1; i < Q; ++i) {
+            const int aa = ((a - L::ex[i]) % NA + NA) % NA, bb = ((b - L::ey[i]) % NB + NB) % NB;
+            const int cc = ((c - L::ez[i]) % NCc + NCc) % NCc;
+            if (emap[((size_t)cc * NB + bb) * NA + aa] < 0) return LBM_ERR_HIP;  // words and mask disagree
+        }
+    }
+    char* ws = h->ws;
+    hipError_t e = hipMemcpyAsync(ws + h->lay.femap, emap.data(), N * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && h->n_ext > 0)
+        e = hipMemcpyAsync(ws + h->lay.fdmap, dmap.data(), (size_t)h->n_ext * 4, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && h->n_ext > 0) {
+        hipLaunchKernelGGL(k_fl_table, dim3(blocks(h->n_ext)), dim3(kFlThreads), 0, h->stream,
+                           reinterpret_cast<const int32_t*>(ws + h->lay.femap),
+                           reinterpret_cast<const int32_t*>(ws + h->lay.fdmap),
+                           reinterpret_cast<int32_t*>(ws + h->lay.ftab), h->n_ext, h->fl_T, h->NA, h->NB, h->NCc);
+        e = hipGetLastError();
+    }
+    // the host vectors must outlive the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+hipError_t lbmi::fluid_init(lbm_handle* h, const void* rho0, const void* u0) {
+    return dispatch<InitFn>(h, rho0, u0);
+}
+
+hipError_t lbmi::fluid_step(lbm_handle* h) { return dispatch<StepFn>(h); }
+
+hipError_t lbmi::fluid_moments(lbm_handle* h, int comp, void* rho, void* u) {
+    return dispatch<MomFn>(h, comp, rho, u);
+}

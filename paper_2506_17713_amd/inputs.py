@@ -67,6 +67,7 @@ class Workload:
     kappa: tuple = (0.0, 0.0)         # surface-tension adjustment (D2Q9 MRT, Eq. 14-16)
     res_rho: tuple = ((0.0, 0.0), (0.0, 0.0))  # fixed densities of reservoirs 0 and 1 (mask 2, 3)
     window: tuple = (0, 0)            # planes of the capillary-pressure measurement (0, 0: all)
+    layout: str = "DENSE"             # "DENSE" or "FLUID" (fluid nodes only: porous media)
     steps: int = 100
     extra: dict = field(default_factory=dict)
 

@@ -19,6 +19,7 @@ LBM_OK = 0
 ERRORS = {-1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP", -4: "LBM_ERR_NONFINITE",
           -5: "LBM_ERR_SPACE", -6: "LBM_ERR_OOM"}
 STORAGE = {"F64": 0, "F32": 1, "F16DEV": 2, "BF16DEV": 3, "F32F64": 4}
+LAYOUT = {"DENSE": 0, "FLUID": 1}  # lbm_params.layout
 EXPORTS = ["lbm_workspace_size", "lbm_init", "lbm_step", "lbm_moments", "lbm_stats", "lbm_sync",
            "lbm_set_reservoir", "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_reset", "lbm_grad_workspace_size", "lbm_grad",
            "lbm_free", "lbm_strerror"]
@@ -42,7 +43,7 @@ class LbmParams(C.Structure):
         ("eos_T", C.c_double * 2), ("alpha", C.c_double * 2), ("A", C.c_double * 2),
         ("g", (C.c_double * 2) * 2), ("body_accel", C.c_double * 3), ("wet", C.c_double * 2),
         ("rho_min", C.c_double * 2), ("rho_max", C.c_double * 2), ("kappa", C.c_double * 2),
-        ("res_rho", (C.c_double * 2) * 2), ("window", C.c_int32 * 2), ("reserved2", C.c_int32 * 2),
+        ("res_rho", (C.c_double * 2) * 2), ("window", C.c_int32 * 2), ("layout", C.c_int32), ("reserved2", C.c_int32),
     ]
 
 
@@ -141,6 +142,7 @@ def params_from(w, check_every: int = 0) -> LbmParams:
     for d in range(3):
         p.body_accel[d] = w.body[d]
     p.window[0], p.window[1] = w.window
+    p.layout = LAYOUT[w.layout]
     return p
 
 

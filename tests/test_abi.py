@@ -190,7 +190,7 @@ def test_init_rejects_bad_reservoir_masks(lib):
     for p_, m in bad:
         assert init(p_, m) == -1
     p = lbm.params_from(w)
-    p.reserved2[0] = 1
+    p.reserved2 = 1
     assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -1
     assert lib.lbm_set_reservoir(None, 0, None) == -1
 
@@ -218,3 +218,32 @@ def test_init_rejects_bad_convective_outlets(lib):
     m = mask.copy(); m[0] = 0                       # fluid above the outlet across the wrap
     assert init(p, m) == -1
     assert init(lbm.params_from(w.with_(storage="F16DEV")), mask) == -2
+
+
+def test_fluid_layout_validation(lib):
+    # LBM_LAYOUT_FLUID: D3Q19, full-precision storage, BGK or MRT, no open
+    # boundaries; the workspace adds the neighbour table
+    sz, szd = C.c_size_t(), C.c_size_t()
+    assert lib.lbm_workspace_size(C.byref(_params(layout="FLUID")), C.byref(sz)) == 0
+    assert lib.lbm_workspace_size(C.byref(_params()), C.byref(szd)) == 0
+    assert sz.value >= szd.value + 18 * 16 ** 3 * 4
+    for kw in (dict(storage="F16DEV"), dict(storage="BF16DEV")):
+        assert lib.lbm_workspace_size(C.byref(_params(layout="FLUID", **kw)), C.byref(sz)) == -2
+    p = _params(layout="FLUID")
+    p.lattice, p.nz = 0, 1                                  # a valid D2Q9 set
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -2
+    p.layout = 0
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == 0
+    p = _params()
+    p.layout = 2
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -1
+    # reservoirs: refused before the GPU is touched
+    w, mask, rho = inputs.pcsw_pack(n=12, buffer=2, shape=(18, 12, 12))
+    p = lbm.params_from(w.with_(layout="FLUID"))
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == 0
+    m = np.ascontiguousarray(mask.reshape(-1).astype(np.uint8))
+    r = np.ascontiguousarray(rho.reshape(2, -1))
+    h = C.c_void_p()
+    rc = lib.lbm_init(C.byref(p), m.ctypes.data, r.ctypes.data, None, None, C.c_void_p(1 << 20), sz.value, None,
+                      C.byref(h))
+    assert rc == -2
