@@ -561,7 +561,7 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
             return LBM_ERR_ARG;
         if (is_dev(p->storage)) return LBM_ERR_UNSUPPORTED;
     }
-    if (has_res && p->layout == LBM_LAYOUT_FLUID) return LBM_ERR_UNSUPPORTED;
+    if (conv_plane >= 0 && p->layout == LBM_LAYOUT_FLUID) return LBM_ERR_UNSUPPORTED;
     size_t n_solid = 0;
     for (size_t n = 0; n < N; ++n) {
         if (mask[n]) {
@@ -593,7 +593,7 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     h->wet_uniform = wet == nullptr;
     h->has_res = has_res;
     h->conv_plane = conv_plane;
-    h->n_fl = h->n_ext = h->fl_T = 0;
+    h->n_fl = h->n_sol = h->n_r1 = h->n_ext = h->fl_T = 0;
     std::memcpy(h->res_active, p->res_rho, sizeof(h->res_active));
     h->mostly_fluid = n_solid * 10 < N;
     // LBM_CHUNK (environment, tuning only): planes per workgroup along the

@@ -16,6 +16,10 @@
 //               collision, store.
 // Both pulls read the neighbour table (ids of x - e_i), one 4-byte index per
 // direction and node; the gather reads psi through the same ids.
+//
+// Ids: [0, n_fl) the fluid nodes, [n_fl, n_sol) the solid nodes next to
+// fluid, [n_sol, n_r1) the nodes of reservoir 0 and [n_r1, n_ext) those of
+// reservoir 1 (open boundaries, whole planes), each range in lattice order.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -42,7 +46,7 @@ struct FlArgs {
     R* rho;               // [NC][T]: density of the fluid ids
     R* psi;               // [NC][T]: psi of every id
     R* U;                 // [NC][T]: U of every id (Zhang-Chen term only)
-    int n_fl, n_ext, T;
+    int n_fl, n_sol, n_r1, n_ext, T;
 };
 
 // Workgroup -> block of ids: consecutive blocks on one XCD (the hardware
@@ -77,6 +81,18 @@ __device__ __forceinline__ void fl_pull(const StepArgs<typename Store<ST>::R>& P
 #pragma unroll
         for (int k = 0; k < NC; ++k) f[k][i] = (R)fin[(size_t)k * Q * T + off];
     });
+    if (A.n_sol < A.n_ext) {
+        // a reservoir source: anti-bounce-back, 2 w_i rho_res - f*_opp(i)(x),
+        // at the density of the streaming this pull completes (Sec. 3.4.3)
+        sfor<Q - 1>([&](auto I) {
+            constexpr int i = decltype(I)::value + 1;
+            if (src[i] >= A.n_sol) {
+                const int r = src[i] >= A.n_r1 ? 1 : 0;
+#pragma unroll
+                for (int k = 0; k < NC; ++k) f[k][i] = (R)(2.0 * L::w(i)) * P.res_abb[r][k] - f[k][i];
+            }
+        });
+    }
 }
 
 // rho^k = sum_i f_i, summed as in the dense kernels (rest, then pairs)
@@ -180,15 +196,28 @@ __global__ void __launch_bounds__(kFlThreads)
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2: virtual density (Eq. 17) and psi of the solid ids: the
-// weight-averaged density of the fluid neighbours x + e_i (in direction
-// order), then phi rho_ave or rho_ave - drho, limited to [rho_min, rho_max].
+// Pass 2: psi of the solid and reservoir ids.  A solid takes the virtual
+// density of Eq. 17: the weight-averaged density of its fluid and reservoir
+// neighbours x + e_i (in direction order), then phi rho_ave or rho_ave -
+// drho, limited to [rho_min, rho_max].  A reservoir node takes its fixed
+// density.
 // ---------------------------------------------------------------------------
 template <int NC, class R>
 __global__ void __launch_bounds__(kFlThreads) k_fl_solid(StepArgs<R> P, FlArgs<R> A) {
     const int s = A.n_fl + blockIdx.x * kFlThreads + threadIdx.x;
     if (s >= A.n_ext) return;
     const size_t T = (size_t)A.T;
+    if (s >= A.n_sol) {
+        const int r = s >= A.n_r1 ? 1 : 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            R ps, u;
+            psi_of(P, k, P.res_rho[r][k], ps, u);
+            A.psi[k * T + s] = ps;
+            if (P.has_zc) A.U[k * T + s] = u;
+        }
+        return;
+    }
     R num[NC], den = 0;
 #pragma unroll
     for (int k = 0; k < NC; ++k) num[k] = 0;
@@ -199,6 +228,11 @@ __global__ void __launch_bounds__(kFlThreads) k_fl_solid(StepArgs<R> P, FlArgs<R
             den += (R)L::w(i);
 #pragma unroll
             for (int k = 0; k < NC; ++k) num[k] += (R)L::w(i) * A.rho[(size_t)k * T + nb];
+        } else if (nb >= A.n_sol) {
+            const int r = nb >= A.n_r1 ? 1 : 0;
+            den += (R)L::w(i);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) num[k] += (R)L::w(i) * P.res_rho[r][k];
         }
     });
     const int n = A.dmap[s];
@@ -394,7 +428,7 @@ __global__ void __launch_bounds__(kFlThreads)
 template <int NC, int ST>
 __global__ void __launch_bounds__(kFlThreads)
     k_fl_init(const typename Store<ST>::R* __restrict__ rho0, const typename Store<ST>::R* __restrict__ u0,
-              FlArgs<typename Store<ST>::R> A, void* fout, int N) {
+              FlArgs<typename Store<ST>::R> A, void* fout, int N, ResRho res) {
     using S = typename Store<ST>::S;
     using R = typename Store<ST>::R;
     const int e = blockIdx.x * kFlThreads + threadIdx.x;
@@ -417,10 +451,15 @@ __global__ void __launch_bounds__(kFlThreads)
                 v = feq(k, n, 0, 0, 0, L::w(0));
             } else {
                 const int32_t nb = A.tab[(size_t)(o - 1) * T + e];  // y + e_i
-                if ((uint32_t)nb < (uint32_t)A.n_fl)
+                if ((uint32_t)nb < (uint32_t)A.n_fl) {
                     v = feq(k, A.dmap[nb], L::ex[i], L::ey[i], L::ez[i], L::w(i));
-                else
+                } else if (nb >= A.n_sol) {
+                    // y + e_i is a reservoir: the value the anti-bounce-back turns into f^eq_o(y)
+                    const R rr = (R)res.r[nb >= A.n_r1 ? 1 : 0][k];
+                    v = (R)(2.0 * L::w(o)) * rr - feq(k, n, L::ex[o], L::ey[o], L::ez[o], L::w(o));
+                } else {
                     v = feq(k, n, L::ex[o], L::ey[o], L::ez[o], L::w(o));
+                }
             }
             out[(size_t)(k * Q + i) * T + e] = (S)v;
         });
@@ -455,6 +494,8 @@ FlArgs<R> fl_args(lbm_handle* h) {
     A.psi = reinterpret_cast<R*>(ws + h->lay.fpsi);
     A.U = reinterpret_cast<R*>(ws + h->lay.fU);
     A.n_fl = h->n_fl;
+    A.n_sol = h->n_sol;
+    A.n_r1 = h->n_r1;
     A.n_ext = h->n_ext;
     A.T = h->fl_T;
     return A;
@@ -511,8 +552,10 @@ template <int NC, int ST>
 hipError_t init_store(lbm_handle* h, const void* rho0, const void* u0) {
     using R = typename Store<ST>::R;
     if (h->n_fl == 0) return hipSuccess;
+    ResRho res;
+    std::memcpy(res.r, h->res_active, sizeof(res.r));
     hipLaunchKernelGGL((k_fl_init<NC, ST>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream,
-                       (const R*)rho0, (const R*)u0, fl_args<R>(h), h->ws + h->lay.fA, h->N);
+                       (const R*)rho0, (const R*)u0, fl_args<R>(h), h->ws + h->lay.fA, h->N, res);
     return hipGetLastError();
 }
 
@@ -548,7 +591,8 @@ struct InitFn {
 int lbmi::fluid_build(lbm_handle* h) {
     const size_t N = (size_t)h->N;
     // which solid nodes have a fluid neighbour: from the neighbour words
-    // (bit 0: the node is solid; bit i: x - e_i is solid)
+    // (bit 0: the node is not fluid; bit i: x - e_i is solid or a reservoir;
+    // NW_OWN_RES / NW_OWN_ID: the node is a reservoir node, of reservoir 1)
     std::vector<uint32_t> word;
     std::vector<int32_t> emap, dmap;
     try {
@@ -569,12 +613,24 @@ int lbmi::fluid_build(lbm_handle* h) {
         }
     h->n_fl = (int)dmap.size();
     for (size_t n = 0; n < N; ++n)
-        if ((word[n] & 1u) && (word[n] & ALLNB) != ALLNB) {
+        if ((word[n] & 1u) && !(word[n] & NW_OWN_RES) && (word[n] & ALLNB) != ALLNB) {
             emap[n] = (int32_t)dmap.size();
             dmap.push_back((int32_t)n);
         }
+    h->n_sol = (int)dmap.size();
+    // every reservoir node (whole planes): reservoir 0, then reservoir 1
+    for (uint32_t id = 0; id < 2; ++id) {
+        if (id == 1) h->n_r1 = (int)dmap.size();
+        for (size_t n = 0; n < N; ++n)
+            if ((word[n] & NW_OWN_RES) && ((word[n] & NW_OWN_ID) ? 1u : 0u) == id) {
+                emap[n] = (int32_t)dmap.size();
+                dmap.push_back((int32_t)n);
+            }
+    }
     h->n_ext = (int)dmap.size();
     h->fl_T = (int)((N + 63) / 64 * 64);
+    // each node is listed at most once, so the ids fit the rows of T
+    if (dmap.size() > N) return LBM_ERR_HIP;
     // every neighbour of a fluid node is listed (fluid, or solid next to
     // fluid), so the pulls and gathers of the step index only listed ids
     const int NA = h->NA, NB = h->NB, NCc = h->NCc;

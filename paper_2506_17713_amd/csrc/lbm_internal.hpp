@@ -65,10 +65,11 @@ struct lbm_handle {
     double res_active[2][2];
     int conv_plane;    // plane of the convective outlet, -1: none
     int chunk_override;
-    // fluid-only layout: nodes 0..n_fl-1 are the fluid nodes in lattice
-    // order, n_fl..n_ext-1 the solid nodes with a fluid neighbour; fl_T is
-    // the row stride of the populations and the table (a multiple of 64)
-    int n_fl, n_ext, fl_T;
+    // fluid-only layout: ids [0, n_fl) are the fluid nodes in lattice order,
+    // [n_fl, n_sol) the solid nodes with a fluid neighbour, [n_sol, n_r1) and
+    // [n_r1, n_ext) the nodes of reservoirs 0 and 1; fl_T is the row stride of
+    // the populations and the table (a multiple of 64)
+    int n_fl, n_sol, n_r1, n_ext, fl_T;
 };
 
 namespace lbmi {

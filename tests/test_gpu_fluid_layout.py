@@ -136,3 +136,68 @@ def test_fluid_layout_grad_is_unsupported():
         s.grad(4, 2)
     assert ei.value.code == -2
     s.close()
+
+
+# ------------------------------------------------ open boundaries: reservoirs
+@pytest.mark.parametrize("storage", ["F64", "F32"])
+def test_drainage_pack_between_reservoirs(oracle_mod, storage):
+    # the capillary pressure - saturation workload at a small size, inlet
+    # pressure raised: anti-bounce-back inflow, reservoir densities in the
+    # force and the virtual densities, capillary slots of lbm_stats
+    from test_gpu_open_boundary import _RHO, check_capillary, check_fields
+
+    w, mask, rho = inputs.pcsw_pack(n=40, buffer=4, storage=storage, dp_rho=0.08, shape=(50, 37, 40))
+    w = fluid(w.with_(name="fl_pcsw_pack"))
+    _RHO[w.name] = rho
+    out, st, _ = run_pair(oracle_mod, w, mask, rho, 300)
+    check_fields(out, storage)
+    check_capillary(oracle_mod, w, mask, st, 300)
+
+
+@pytest.mark.parametrize("storage", ["F64", "F32"])
+def test_liquid_reservoir_imbibition_mrt(oracle_mod, storage):
+    # one CS component at T_r = 0.8 with the Zhang-Chen term, d'Humieres MRT
+    # at tau = 0.8: a vapour tube between a liquid reservoir below and a
+    # vapour reservoir above
+    from test_gpu_open_boundary import _RHO, check_capillary, check_fields
+
+    coex = inputs.load_coexistence()["CS"]["0.8"]
+    T, rv, rl, A = coex["T"], coex["rho_v"], coex["rho_l"], coex["A"]
+    shape = (30, 11, 70)
+    mask = np.zeros(shape, np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, :, 0] = 1
+    mask[0], mask[-1] = 2, 3
+    z = np.arange(shape[0])[:, None, None] * np.ones(shape)
+    rho = inputs.tanh_profile(z, 6.0, 4.0, rl, rv)[None]
+    dh = inputs.dhumieres_rates(0.8)
+    w = inputs.Workload("fl_imbibition3d", "D3Q19", shape, storage=storage, collision="MRT", tau=(0.8, 0.8),
+                        mrt_s=(dh, dh), eos_T=(T, T), A=(A, A), wet=(1.1, 1.1), rho_min=(rv, rv), rho_max=(rl, rl),
+                        res_rho=((rl, rl), (rv, rv)), window=(2, 28), layout="FLUID")
+    _RHO[w.name] = rho
+    out, st, _ = run_pair(oracle_mod, w, mask, rho, 300)
+    check_fields(out, storage)
+    check_capillary(oracle_mod, w, mask, st, 300)
+
+
+def test_set_reservoir_between_steps(oracle_mod):
+    from paper_2506_17713_amd import lbm
+
+    w, mask, rho = inputs.pcsw_pack(n=24, buffer=3, storage="F64", shape=(32, 20, 24))
+    w = fluid(w)
+    print(f"case fluid set_reservoir {w.shape}", flush=True)
+    sol = lbm.Solver(w, mask, rho)
+    ref = oracle_mod.State(w, mask, rho)
+    sol.step(60)
+    ref.step(60)
+    sol.set_reservoir(0, (1.12, 0.03))
+    ref.set_reservoir(0, (1.12, 0.03))
+    sol.step(60)
+    ref.step(60)
+    r_gpu, u_gpu = sol.moments_numpy(-1)
+    sol.close()
+    fl = ref.fields()
+    fluid_nodes = mask.reshape(-1) == 0
+    r_ref = np.where(fluid_nodes, fl["rho"].sum(0), 0.0)
+    assert np.abs(r_gpu - r_ref).max() < 1e-10 * r_ref.max()
+    assert np.abs(u_gpu - fl["umix"]).max() < 1e-10 * np.abs(fl["umix"]).max()
