@@ -43,9 +43,11 @@ struct FlArgs {
     const int32_t* tab;   // [Q-1][T]: id of x - e_i (ids >= n_fl: solid; -1: solid without fluid neighbour)
     const int32_t* dmap;  // [T]: lattice index of id
     const int32_t* emap;  // [N]: id of lattice node, -1 for a solid without fluid neighbour
-    R* rho;               // [NC][T]: density of the fluid ids
-    R* psi;               // [NC][T]: psi of every id
-    R* U;                 // [NC][T]: U of every id (Zhang-Chen term only)
+    // per-id values with the components adjacent ([T][NC]), so that one
+    // gather of a neighbour loads every component
+    R* rho;               // [T][NC]: density of the fluid ids
+    R* psi;               // [T][NC]: psi of every id
+    R* U;                 // [T][NC]: U of every id (Zhang-Chen term only)
     int n_fl, n_sol, n_r1, n_ext, T;
 };
 
@@ -57,6 +59,26 @@ __device__ __forceinline__ int xcd_block() {
     const int per = nblk >> 3, rem = nblk & 7, xcd = bid & 7;
     return xcd * per + (xcd < rem ? xcd : rem) + (bid >> 3);
 }
+
+// The NC values of one id, loaded together (one 8- or 16-byte load for two
+// components).
+template <class R, int NC>
+struct Comp {
+    R v[NC];
+    __device__ __forceinline__ static Comp load(const R* p) {
+        Comp c;
+        if constexpr (NC == 2) {
+            using V = R __attribute__((ext_vector_type(2)));
+            const V x = *reinterpret_cast<const V*>(p);
+            c.v[0] = x[0];
+            c.v[1] = x[1];
+        } else {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) c.v[k] = p[k];
+        }
+        return c;
+    }
+};
 
 // Neighbour ids src[i] of x - e_i (src[0] = the node itself) and the pull
 // f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) where x - e_i is solid.
@@ -113,7 +135,6 @@ template <int NC, class R>
 __device__ __forceinline__ void fl_moments_force(const StepArgs<R>& P, const FlArgs<R>& A, int e,
                                                  const int32_t (&src)[Q], const R (&f)[NC][Q], R (&rho)[NC],
                                                  R (&j)[NC][3], R (&F)[NC][3]) {
-    const size_t T = (size_t)A.T;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         R r = f[k][0], dl[NP];
@@ -127,27 +148,35 @@ __device__ __forceinline__ void fl_moments_force(const StepArgs<R>& P, const FlA
         pair_sums<LAT_D3Q19, -1>(dl, j[k]);
     }
     // D^kk = sum_i G_i psi^kk(x + e_i) e_i as differences across opposite
-    // neighbours; x + e_i = x - e_opp(i) is src[i + 1] for odd i
+    // neighbours; x + e_i = x - e_opp(i) is src[i + 1] for odd i.  All
+    // components of a neighbour come with one load.
     constexpr R G0 = (R)(3.0 * L::w(1));
     constexpr R G1 = (R)(3.0 * L::w(Q - 1));
-    auto gather = [&](const R* arr, int kk, R(&out)[3]) {
-        R dv[NP];
+    auto gather = [&](const R* arr, R(&out)[NC][3]) {
+        R dv[NC][NP];
         sfor<NP>([&](auto PI) {
             constexpr int i = 2 * decltype(PI)::value + 1;
-            dv[decltype(PI)::value] = arr[(size_t)kk * T + (uint32_t)src[i + 1]] - arr[(size_t)kk * T + (uint32_t)src[i]];
-        });
-        R s0[3], s1[3];
-        pair_sums<LAT_D3Q19, 0>(dv, s0);
-        pair_sums<LAT_D3Q19, 1>(dv, s1);
+            const Comp<R, NC> vp = Comp<R, NC>::load(arr + (size_t)(uint32_t)src[i + 1] * NC);
+            const Comp<R, NC> vm = Comp<R, NC>::load(arr + (size_t)(uint32_t)src[i] * NC);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) out[d] = G0 * s0[d] + G1 * s1[d];
+            for (int kk = 0; kk < NC; ++kk) dv[kk][decltype(PI)::value] = vp.v[kk] - vm.v[kk];
+        });
+#pragma unroll
+        for (int kk = 0; kk < NC; ++kk) {
+            R s0[3], s1[3];
+            pair_sums<LAT_D3Q19, 0>(dv[kk], s0);
+            pair_sums<LAT_D3Q19, 1>(dv[kk], s1);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) out[kk][d] = G0 * s0[d] + G1 * s1[d];
+        }
     };
     R Dps[NC][3];
-#pragma unroll
-    for (int kk = 0; kk < NC; ++kk) gather(A.psi, kk, Dps[kk]);
+    gather(A.psi, Dps);
+    R zu[NC][3];
+    if (P.has_zc) gather(A.U, zu);
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        const R psik = A.psi[(size_t)k * T + e];
+        const R psik = A.psi[(size_t)e * NC + k];
         const R Bk = (R)1 - P.A[k];
         R sv[3];
 #pragma unroll
@@ -162,11 +191,9 @@ __device__ __forceinline__ void fl_moments_force(const StepArgs<R>& P, const FlA
         F[k][1] = cpsi * sv[1] + rho[k] * P.body[1];
         F[k][2] = cpsi * sv[2] + rho[k] * P.body[2];
         if (P.has_zc) {
-            R zu[3];
-            gather(A.U, k, zu);
-            F[k][0] -= P.A[k] * zu[0];
-            F[k][1] -= P.A[k] * zu[1];
-            F[k][2] -= P.A[k] * zu[2];
+            F[k][0] -= P.A[k] * zu[k][0];
+            F[k][1] -= P.A[k] * zu[k][1];
+            F[k][2] -= P.A[k] * zu[k][2];
         }
     }
 }
@@ -189,9 +216,9 @@ __global__ void __launch_bounds__(kFlThreads)
         const R r = fl_rho_sum<NC>(f, k);
         R ps, u;
         psi_of(P, k, r, ps, u);
-        A.rho[k * T + e] = r;
-        A.psi[k * T + e] = ps;
-        if (P.has_zc) A.U[k * T + e] = u;
+        A.rho[(size_t)e * NC + k] = r;
+        A.psi[(size_t)e * NC + k] = ps;
+        if (P.has_zc) A.U[(size_t)e * NC + k] = u;
     }
 }
 
@@ -213,8 +240,8 @@ __global__ void __launch_bounds__(kFlThreads) k_fl_solid(StepArgs<R> P, FlArgs<R
         for (int k = 0; k < NC; ++k) {
             R ps, u;
             psi_of(P, k, P.res_rho[r][k], ps, u);
-            A.psi[k * T + s] = ps;
-            if (P.has_zc) A.U[k * T + s] = u;
+            A.psi[(size_t)s * NC + k] = ps;
+            if (P.has_zc) A.U[(size_t)s * NC + k] = u;
         }
         return;
     }
@@ -227,7 +254,7 @@ __global__ void __launch_bounds__(kFlThreads) k_fl_solid(StepArgs<R> P, FlArgs<R
         if ((uint32_t)nb < (uint32_t)A.n_fl) {
             den += (R)L::w(i);
 #pragma unroll
-            for (int k = 0; k < NC; ++k) num[k] += (R)L::w(i) * A.rho[(size_t)k * T + nb];
+            for (int k = 0; k < NC; ++k) num[k] += (R)L::w(i) * A.rho[(size_t)nb * NC + k];
         } else if (nb >= A.n_sol) {
             const int r = nb >= A.n_r1 ? 1 : 0;
             den += (R)L::w(i);
@@ -247,8 +274,8 @@ __global__ void __launch_bounds__(kFlThreads) k_fl_solid(StepArgs<R> P, FlArgs<R
             rsv = rsv > P.rho_max[k] ? P.rho_max[k] : rsv;
             psi_of(P, k, rsv, ps, u);
         }
-        A.psi[k * T + s] = ps;
-        if (P.has_zc) A.U[k * T + s] = u;
+        A.psi[(size_t)s * NC + k] = ps;
+        if (P.has_zc) A.U[(size_t)s * NC + k] = u;
     }
 }
 
