@@ -72,9 +72,9 @@ enum { LBM_WET_PHI = 0, LBM_WET_DRHO = 1 };
  * table of the 18 neighbour indices per fluid node and per solid node next to
  * fluid (porous media: at porosity 0.35 the dense rows carry about three
  * times the fluid bytes).  Same method and results as DENSE (pinned by the
- * parity tests); D3Q19 only, storage F64, F32 or F32_F64, BGK or MRT,
- * reservoirs but no convective outlet (LBM_ERR_UNSUPPORTED otherwise), and
- * lbm_grad is LBM_ERR_UNSUPPORTED.  The state of lbm_get_state / lbm_set_state is the
+ * parity tests); D3Q19 only, any storage, BGK or MRT, reservoirs but no
+ * convective outlet (LBM_ERR_UNSUPPORTED otherwise), and lbm_grad is
+ * LBM_ERR_UNSUPPORTED.  The state of lbm_get_state / lbm_set_state is the
  * fluid-node populations (lbm_state_bytes). */
 enum { LBM_LAYOUT_DENSE = 0, LBM_LAYOUT_FLUID = 1 };
 

@@ -53,9 +53,8 @@ int validate(const lbm_params* p) {
         if (p->reserved[i] != 0) return LBM_ERR_ARG;
     if (p->reserved2 != 0) return LBM_ERR_ARG;
     if (p->layout != LBM_LAYOUT_DENSE && p->layout != LBM_LAYOUT_FLUID) return LBM_ERR_ARG;
-    // fluid-only layout: D3Q19, full-precision storage, BGK or MRT
-    if (p->layout == LBM_LAYOUT_FLUID &&
-        (p->lattice != LBM_D3Q19 || is_dev(p->storage) || p->collision == LBM_CLBM))
+    // fluid-only layout: D3Q19, BGK or MRT
+    if (p->layout == LBM_LAYOUT_FLUID && (p->lattice != LBM_D3Q19 || p->collision == LBM_CLBM))
         return LBM_ERR_UNSUPPORTED;
     for (int k = 0; k < p->n_comp; ++k) {
         if (!(p->tau[k] > 0.5) || !std::isfinite(p->tau[k])) return LBM_ERR_ARG;
@@ -109,8 +108,8 @@ Layout layout_of(const lbm_params* p) {
     const size_t pop = nc * q * NT * sb;
     L.fA = take(pop);
     L.fB = take(pop > stage ? pop : stage);
-    L.rA = take(is_dev(p->storage) ? nc * N * 4 : 0);
-    L.rB = take(is_dev(p->storage) ? nc * N * 4 : 0);
+    L.rA = take(is_dev(p->storage) ? nc * NT * 4 : 0);
+    L.rB = take(is_dev(p->storage) ? nc * NT * 4 : 0);
     L.nbr = take(N * 4);
     L.wet = take(nc * N * rb);
     L.mrho = take(nc * N * rb);

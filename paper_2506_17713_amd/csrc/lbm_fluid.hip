@@ -81,13 +81,17 @@ struct Comp {
 };
 
 // Neighbour ids src[i] of x - e_i (src[0] = the node itself) and the pull
-// f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) where x - e_i is solid.
+// f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) where x - e_i is solid.  With
+// deviation storage the stored value is h = f* / (w_i rho*) - 1 with rho*
+// the density of the node that stored it ([T][NC] in P.rin), and the pull
+// rebuilds f = w_i rho* (1 + h) as the dense kernels do.
 template <int NC, int ST>
 __device__ __forceinline__ void fl_pull(const StepArgs<typename Store<ST>::R>& P,
                                         const FlArgs<typename Store<ST>::R>& A, int e, int32_t (&src)[Q],
                                         typename Store<ST>::R (&f)[NC][Q]) {
-    using S = typename Store<ST>::S;
-    using R = typename Store<ST>::R;
+    using SS = Store<ST>;
+    using S = typename SS::S;
+    using R = typename SS::R;
     const size_t T = (size_t)A.T;
     const S* fin = reinterpret_cast<const S*>(P.fin);
     src[0] = e;
@@ -100,8 +104,15 @@ __device__ __forceinline__ void fl_pull(const StepArgs<typename Store<ST>::R>& P
         // a solid source (id >= n_fl, or -1) bounces back the node's own opposite population
         const bool bb = i != 0 && (uint32_t)src[i] >= (uint32_t)A.n_fl;
         const size_t off = bb ? (size_t)opp(i) * T + e : (size_t)i * T + (uint32_t)src[i];
+        if constexpr (SS::DEV) {
+            const Comp<float, NC> rs = Comp<float, NC>::load(P.rin + (size_t)(bb ? e : src[i]) * NC);
 #pragma unroll
-        for (int k = 0; k < NC; ++k) f[k][i] = (R)fin[(size_t)k * Q * T + off];
+            for (int k = 0; k < NC; ++k)
+                f[k][i] = (float)L::w(i) * rs.v[k] * (1.0f + SS::load(fin[(size_t)k * Q * T + off]));
+        } else {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) f[k][i] = (R)fin[(size_t)k * Q * T + off];
+        }
     });
     if (A.n_sol < A.n_ext) {
         // a reservoir source: anti-bounce-back, 2 w_i rho_res - f*_opp(i)(x),
@@ -396,8 +407,23 @@ __global__ void __launch_bounds__(kFlThreads)
             m += fo[i] + fo[i + 1];
         });
         fo[0] = r - m;
+        if constexpr (Store<ST>::DEV) {
+            using SS = Store<ST>;
+            const float ir = 1.0f / r;
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr float iw = (float)(1.0 / L::w(i));
+                __builtin_nontemporal_store((S)SS::cvt(fo[i] * (iw * ir) - 1.0f), out + ((size_t)(k * Q + i)) * T + e);
+            });
+        } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) __builtin_nontemporal_store((S)fo[i], out + ((size_t)(k * Q + i)) * T + e);
+            for (int i = 0; i < Q; ++i) __builtin_nontemporal_store((S)fo[i], out + ((size_t)(k * Q + i)) * T + e);
+        }
+    }
+    if constexpr (Store<ST>::DEV) {
+        // rho* of this node's stored deviations, the components adjacent
+#pragma unroll
+        for (int k = 0; k < NC; ++k) P.rout[(size_t)e * NC + k] = rho[k];
     }
 }
 
@@ -455,9 +481,10 @@ __global__ void __launch_bounds__(kFlThreads)
 template <int NC, int ST>
 __global__ void __launch_bounds__(kFlThreads)
     k_fl_init(const typename Store<ST>::R* __restrict__ rho0, const typename Store<ST>::R* __restrict__ u0,
-              FlArgs<typename Store<ST>::R> A, void* fout, int N, ResRho res) {
-    using S = typename Store<ST>::S;
-    using R = typename Store<ST>::R;
+              FlArgs<typename Store<ST>::R> A, void* fout, float* rout, int N, ResRho res) {
+    using SS = Store<ST>;
+    using S = typename SS::S;
+    using R = typename SS::R;
     const int e = blockIdx.x * kFlThreads + threadIdx.x;
     if (e >= A.n_fl) return;
     const size_t T = (size_t)A.T;
@@ -470,6 +497,8 @@ __global__ void __launch_bounds__(kFlThreads)
         return (R)wi * r * ((R)1 + (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * (ux * ux + uy * uy + uz * uz));
     };
     for (int k = 0; k < NC; ++k) {
+        const R r0 = rho0[(size_t)k * N + n];
+        if constexpr (SS::DEV) rout[(size_t)e * NC + k] = (float)r0;
         sfor<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int o = opp(i);
@@ -488,7 +517,10 @@ __global__ void __launch_bounds__(kFlThreads)
                     v = feq(k, n, L::ex[o], L::ey[o], L::ez[o], L::w(o));
                 }
             }
-            out[(size_t)(k * Q + i) * T + e] = (S)v;
+            if constexpr (SS::DEV)
+                out[(size_t)(k * Q + i) * T + e] = SS::cvt((float)v / ((float)L::w(i) * (float)r0) - 1.0f);
+            else
+                out[(size_t)(k * Q + i) * T + e] = (S)v;
         });
     }
 }
@@ -581,12 +613,14 @@ hipError_t init_store(lbm_handle* h, const void* rho0, const void* u0) {
     if (h->n_fl == 0) return hipSuccess;
     ResRho res;
     std::memcpy(res.r, h->res_active, sizeof(res.r));
+    float* rout = is_dev(h->p.storage) ? reinterpret_cast<float*>(h->ws + h->lay.rA) : nullptr;
     hipLaunchKernelGGL((k_fl_init<NC, ST>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream,
-                       (const R*)rho0, (const R*)u0, fl_args<R>(h), h->ws + h->lay.fA, h->N, res);
+                       (const R*)rho0, (const R*)u0, fl_args<R>(h), h->ws + h->lay.fA, rout, h->N, res);
     return hipGetLastError();
 }
 
-// Dispatch over components and storage (F64, F32, F32 with FP64 arithmetic).
+// Dispatch over components and storage (F64, F32, F32 with FP64 arithmetic,
+// FP16 and BF16 deviations).
 template <template <int, int> class Fn, class... Args>
 hipError_t dispatch(lbm_handle* h, Args... args) {
     const int nc = h->p.n_comp;
@@ -597,6 +631,10 @@ hipError_t dispatch(lbm_handle* h, Args... args) {
             return nc == 1 ? Fn<1, ST_F32>::run(h, args...) : Fn<2, ST_F32>::run(h, args...);
         case LBM_STORE_F32_F64:
             return nc == 1 ? Fn<1, ST_F32D>::run(h, args...) : Fn<2, ST_F32D>::run(h, args...);
+        case LBM_STORE_F16DEV:
+            return nc == 1 ? Fn<1, ST_F16>::run(h, args...) : Fn<2, ST_F16>::run(h, args...);
+        case LBM_STORE_BF16DEV:
+            return nc == 1 ? Fn<1, ST_BF16>::run(h, args...) : Fn<2, ST_BF16>::run(h, args...);
         default: return hipErrorInvalidValue;  // rejected at lbm_init
     }
 }

@@ -221,14 +221,16 @@ def test_init_rejects_bad_convective_outlets(lib):
 
 
 def test_fluid_layout_validation(lib):
-    # LBM_LAYOUT_FLUID: D3Q19, full-precision storage, BGK or MRT, no
-    # convective outlet; the workspace adds the neighbour table
+    # LBM_LAYOUT_FLUID: D3Q19, BGK or MRT, no convective outlet; the
+    # workspace adds the neighbour table
     sz, szd = C.c_size_t(), C.c_size_t()
     assert lib.lbm_workspace_size(C.byref(_params(layout="FLUID")), C.byref(sz)) == 0
     assert lib.lbm_workspace_size(C.byref(_params()), C.byref(szd)) == 0
     assert sz.value >= szd.value + 18 * 16 ** 3 * 4
     for kw in (dict(storage="F16DEV"), dict(storage="BF16DEV")):
-        assert lib.lbm_workspace_size(C.byref(_params(layout="FLUID", **kw)), C.byref(sz)) == -2
+        assert lib.lbm_workspace_size(C.byref(_params(layout="FLUID", **kw)), C.byref(sz)) == 0
+    p = _params(layout="FLUID", collision="CLBM")
+    assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -2
     p = _params(layout="FLUID")
     p.lattice, p.nz = 0, 1                                  # a valid D2Q9 set
     assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -2
