@@ -7,9 +7,11 @@ virtual-density wetting (phi = 1.1).  A step is one launch of the fused
 kernel (moments, virtual densities, pseudopotential, force, MRT collision with
 exact-difference forcing, pull streaming with bounce-back).
 
---workload droplet2d (D2Q9 BGK FP64 droplet, 128^2) and --workload pack2
-(two-component D3Q19 sphere pack, 400^3, BGK) time the other configurations
-the same way.
+--workload droplet2d (D2Q9 BGK FP64 droplet, 128^2), --workload pack2
+(two-component D3Q19 sphere pack, 400^3, BGK) and --workload pcsw (the
+two-component drainage pack between reservoirs, 256^3 + buffers) time the
+other configurations the same way; the two packs run on the fluid-only layout
+(three kernels per step) unless --layout DENSE is given.
 
 Prints one JSON line: MLUPS (n_components * nx * ny * nz * steps / time / 1e6,
 all nodes counted as the paper does), the HBM roofline of the fused kernel
@@ -48,8 +50,9 @@ def parse():
                          "every 100)")
     ap.add_argument("--storage", default="F32", choices=["F32", "F64", "F32F64", "F16DEV", "BF16DEV"])
     ap.add_argument("--collision", default="MRT", choices=["MRT", "BGK"])
-    ap.add_argument("--layout", default="DENSE", choices=["DENSE", "FLUID"],
-                    help="population layout: every node (DENSE) or fluid nodes only (FLUID, porous media)")
+    ap.add_argument("--layout", default=None, choices=["DENSE", "FLUID"],
+                    help="population layout: every node (DENSE) or fluid nodes only (FLUID); default FLUID for "
+                         "the porous packs (pack2, pcsw), DENSE otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-table", action="store_true",
@@ -413,8 +416,9 @@ def main():
     storage = args.storage if args.workload != "droplet2d" or args.storage != "F32" else "F64"
     collision = "BGK" if args.workload != "sessile" else args.collision
     w, solid, rho, desc = make_workload(args.workload, n, storage, collision)
-    if args.layout != "DENSE":
-        w = w.with_(layout=args.layout)
+    layout = args.layout or ("FLUID" if args.workload in ("pack2", "pcsw") else "DENSE")
+    if layout != "DENSE":
+        w = w.with_(layout=layout)
         desc += ", fluid-only layout"
     sol = lbm.Solver(w, solid, rho, device="cuda:0")
     stream = sol.stream
