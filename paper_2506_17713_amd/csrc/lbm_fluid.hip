@@ -542,6 +542,16 @@ __global__ void __launch_bounds__(kFlThreads)
     });
 }
 
+// Flag (any thread may write it) if a fluid id has an unlisted neighbour.
+__global__ void __launch_bounds__(kFlThreads)
+    k_fl_check(const int32_t* __restrict__ tab, int n_fl, int T, int32_t* __restrict__ flag) {
+    const int e = blockIdx.x * kFlThreads + threadIdx.x;
+    if (e >= n_fl) return;
+    bool bad = false;
+    for (int i = 0; i < Q - 1; ++i) bad |= tab[(size_t)i * T + e] < 0;
+    if (bad) *flag = 1;
+}
+
 template <class R>
 FlArgs<R> fl_args(lbm_handle* h) {
     FlArgs<R> A;
@@ -696,18 +706,6 @@ int lbmi::fluid_build(lbm_handle* h) {
     h->fl_T = (int)((N + 63) / 64 * 64);
     // each node is listed at most once, so the ids fit the rows of T
     if (dmap.size() > N) return LBM_ERR_HIP;
-    // every neighbour of a fluid node is listed (fluid, or solid next to
-    // fluid), so the pulls and gathers of the step index only listed ids
-    const int NA = h->NA, NB = h->NB, NCc = h->NCc;
-    for (int e = 0; e < h->n_fl; ++e) {
-        const int n = dmap[e];
-        const int a = n % NA, b = (n / NA) % NB, c = n / (NA * NB);
-        for (int i = 1; i < Q; ++i) {
-            const int aa = ((a - L::ex[i]) % NA + NA) % NA, bb = ((b - L::ey[i]) % NB + NB) % NB;
-            const int cc = ((c - L::ez[i]) % NCc + NCc) % NCc;
-            if (emap[((size_t)cc * NB + bb) * NA + aa] < 0) return LBM_ERR_HIP;  // words and mask disagree
-        }
-    }
     char* ws = h->ws;
     hipError_t e = hipMemcpyAsync(ws + h->lay.femap, emap.data(), N * 4, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess && h->n_ext > 0)
@@ -719,9 +717,23 @@ int lbmi::fluid_build(lbm_handle* h) {
                            reinterpret_cast<int32_t*>(ws + h->lay.ftab), h->n_ext, h->fl_T, h->NA, h->NB, h->NCc);
         e = hipGetLastError();
     }
+    // every neighbour of a fluid node must be listed (fluid, solid next to
+    // fluid, or reservoir), so that the step's pulls and gathers index only
+    // listed ids; k_fl_check raises a flag (kept in the first word of the
+    // density array, which the first step overwrites) where one is not
+    int32_t* flag = reinterpret_cast<int32_t*>(ws + h->lay.frho);
+    if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 4, h->stream);
+    if (e == hipSuccess && h->n_fl > 0) {
+        hipLaunchKernelGGL(k_fl_check, dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream,
+                           reinterpret_cast<const int32_t*>(ws + h->lay.ftab), h->n_fl, h->fl_T, flag);
+        e = hipGetLastError();
+    }
+    int32_t bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, h->stream);
     // the host vectors must outlive the copies
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+    if (e != hipSuccess) return LBM_ERR_HIP;
+    return bad ? LBM_ERR_HIP : LBM_OK;  // neighbour words and listing disagree
 }
 
 hipError_t lbmi::fluid_init(lbm_handle* h, const void* rho0, const void* u0) {

@@ -225,7 +225,7 @@ NU = (1.0 - 0.5) / 3.0  # BGK tau = 1
 
 
 def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, rho0=None, tol=1e-6, check=100, max_steps=100000,
-                 device="cuda", storage="F64", k_tol=1e-4):
+                 device="cuda", storage="F64", k_tol=1e-4, layout="DENSE"):
     """Run single-phase flow (BGK tau = 1, body acceleration along x) from
     f^eq(rho0, u0) (rest at rho = 1 by default; host arrays, or device
     tensors of the compute type as from warm_start_device) until the residual
@@ -238,8 +238,10 @@ def solve_steady(solid: np.ndarray, accel=1e-5, u0=None, rho0=None, tol=1e-6, ch
     time-to-permeability stopping rule, which needs no converged answer.
     Returns dict(u [3, N] and rho [N] torch tensors, steps, seconds, k,
     residual, k_steps, k_seconds, k_at_k_steps, history of (steps, residual,
-    k, seconds) per check)."""
+    k, seconds) per check).  layout="FLUID" stores the fluid nodes only
+    (lbm_params.layout: the same step, faster on packs)."""
     w, solid, rho = inputs.single_phase_pack(shape=solid.shape, solid=solid, accel=accel, storage=storage)
+    w = w.with_(layout=layout)
     on_device = isinstance(rho0, torch.Tensor)
     if rho0 is not None and not on_device:
         rho = np.asarray(rho0, dtype=np.float64).reshape(rho.shape)

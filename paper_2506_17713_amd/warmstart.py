@@ -42,13 +42,13 @@ from .surrogate import (NU, Surrogate, calibrate_flow, first_within, make_datase
 
 
 def evaluate(model: Surrogate, n_test: int, size: int, accel=1e-5, seed0=1000, first=0, log=print,
-             warm_max_steps=100000):
+             warm_max_steps=100000, layout="FLUID"):
     rng = np.random.default_rng(777)
     pors = [float(rng.uniform(0.3, 0.5)) for _ in range(first + n_test)]
     out = []
     for s in range(first, first + n_test):
         solid = inputs.sphere_pack((size,) * 3, (6.0, 14.0), pors[s], seed0 + s)
-        cold = solve_steady(solid, accel=accel)
+        cold = solve_steady(solid, accel=accel, layout=layout)
         mask = torch.tensor((solid == 0).astype(np.float32)[None], device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -57,7 +57,7 @@ def evaluate(model: Surrogate, n_test: int, size: int, accel=1e-5, seed0=1000, f
         t_inf = time.perf_counter() - t0
         # the network's own k: nu <u_x>_V / a of the predicted velocity
         k_pred = float(((u0[0] + 0.5 * accel) * mask.reshape(-1)).sum()) * NU / accel / solid.size
-        warm = solve_steady(solid, accel=accel, u0=u0, rho0=rho0, max_steps=warm_max_steps)
+        warm = solve_steady(solid, accel=accel, u0=u0, rho0=rho0, max_steps=warm_max_steps, layout=layout)
         kc = cold["k"]
         c1 = first_within(cold["history"], kc) or (cold["steps"], cold["seconds"])
         w1 = first_within(warm["history"], kc) or (warm["steps"], warm["seconds"])
@@ -119,6 +119,8 @@ def parse_args(argv=None) -> argparse.Namespace:
     ap.add_argument("--augment", action="store_true", help="train under random symmetries of the problem")
     ap.add_argument("--warm-max-steps", type=int, default=100000,
                     help="cap on the warm runs (the residual rule may then be left unreached)")
+    ap.add_argument("--layout", default="FLUID", choices=["FLUID", "DENSE"],
+                    help="population layout of the held-out solves (FLUID: fluid nodes only)")
     ap.add_argument("--calibrate", type=int, default=None,
                     help="training-distribution packs for the velocity gain (default: the training set after "
                          "training; 0 keeps the model's gain)")
@@ -164,7 +166,8 @@ def main(argv=None):
     if a.save_model:
         np.savez(a.save_model, **model.state())
     if a.test > 0:
-        res = evaluate(model, a.test, a.test_size, first=a.test_first, log=log, warm_max_steps=a.warm_max_steps)
+        res = evaluate(model, a.test, a.test_size, first=a.test_first, log=log, warm_max_steps=a.warm_max_steps,
+                       layout=a.layout)
         summ["test"] = res
         summ.update(summarise(res))
     with open(a.out, "w") as fh:
