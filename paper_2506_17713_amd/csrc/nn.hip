@@ -519,6 +519,69 @@ __global__ void __launch_bounds__(64)
     }
 }
 
+// The same partial tiles from the BF16 copies with the gfx950 32x32x16 MFMA,
+// for rows of a multiple of 8 positions: a lane half takes 8 consecutive
+// positions of one row, so its dY operand is one aligned 16-byte load and
+// its X operand, shifted by the tap's dx (periodic in x), is formed from two
+// aligned 16-byte loads of the shifted row by a one-element funnel shift.
+// The position coordinates are computed once per 8 positions.  chunk is a
+// multiple of 16 and P of 8, so a half is wholly inside or outside [p0, p1).
+__device__ __forceinline__ s16x8 load16(const short* p) { return *reinterpret_cast<const s16x8*>(p); }
+
+__global__ void __launch_bounds__(64)
+    k_wgrad_w8(const short* __restrict__ Xh, int cin, const short* __restrict__ dYh, int cout, int D, int H, int W,
+               int chunk, float* __restrict__ partial) {
+    const int lane = threadIdx.x;
+    const int P = D * H * W;
+    const int co0 = blockIdx.x * 32, n0 = blockIdx.y * 32, ch = blockIdx.z;
+    const int kq = lane >> 5;
+    const int NN = cin * 27;
+    const int m = co0 + (lane & 31);
+    const int n = n0 + (lane & 31);
+    const bool mok = m < cout, nok = n < NN;
+    const int ci = nok ? n / 27 : 0, tap = nok ? n % 27 : 0;
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int p0 = ch * chunk, p1 = (p0 + chunk < P) ? p0 + chunk : P;
+    const short* xrow = Xh + (size_t)ci * P;
+    const short* yrow = dYh + (size_t)m * P;
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    const s16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int pk = p0; pk < p1; pk += 16) {
+        const int p = pk + 8 * kq;  // this half's 8 positions, one row
+        s16x8 a = zero, b = zero;
+        if (p < p1) {
+            const int x0 = p % W, y = (p / W) % H, z = p / (W * H);
+            if (mok) a = load16(yrow + p);
+            if (nok) {
+                const short* row = xrow + (size_t)(wrapc(z + dz, D) * H + wrapc(y + dy, H)) * W;
+                const s16x8 cur = load16(row + x0);
+                if (dx == 0) {
+                    b = cur;
+                } else {
+                    // neighbouring run of the row (wrapping) and one-element shift
+                    const int xo = dx > 0 ? (x0 + 8 == W ? 0 : x0 + 8) : (x0 == 0 ? W - 8 : x0 - 8);
+                    const s16x8 nb = load16(row + xo);
+                    if (dx > 0) {
+                        b = __builtin_shufflevector(cur, nb, 1, 2, 3, 4, 5, 6, 7, 8);
+                    } else {
+                        b = __builtin_shufflevector(nb, cur, 7, 8, 9, 10, 11, 12, 13, 14);
+                    }
+                }
+            }
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int co = co0 + 8 * (v / 4) + 4 * kq + (v % 4);
+        const int nn = n0 + (lane & 31);
+        if (co < cout && nn < NN) partial[((size_t)ch * cout + co) * NN + nn] = acc[v];
+    }
+}
+
 __global__ void k_chunk_sum(const float* __restrict__ partial, int nchunk, int64_t n, float* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -982,7 +1045,10 @@ int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, in
     if (!X || !dY || !dW || !partial || c_in < 1 || c_out < 1) return LBM_ERR_ARG;
     const int64_t P = (int64_t)D * H * W;
     const int nch = wgrad_chunks(P);
-    const int KS = prec == LBM_NN_BF16 ? 8 : 2;
+    // rows of a multiple of 8 positions take the 16-position steps of k_wgrad_w8
+    // (its 16-byte operand loads need the BF16 copies 16-byte aligned)
+    const bool w8 = prec == LBM_NN_BF16 && W % 8 == 0 && (reinterpret_cast<uintptr_t>(partial) & 15u) == 0;
+    const int KS = w8 ? 16 : (prec == LBM_NN_BF16 ? 8 : 2);
     int chunk = (int)((P + nch - 1) / nch);
     chunk = (chunk + KS - 1) / KS * KS;
     dim3 grid((unsigned)((c_out + 31) / 32), (unsigned)((c_in * 27 + 31) / 32), (unsigned)nch);
@@ -993,8 +1059,12 @@ int lbm_nn_wgrad(const float* X, int c_in, const float* dY, int c_out, int D, in
         hipLaunchKernelGGL(k_to_bf16, dim3(grid1((int64_t)c_in * P)), dim3(256), 0, st, X, Xh, (int64_t)c_in * P);
         hipLaunchKernelGGL(k_to_bf16, dim3(grid1((int64_t)c_out * P)), dim3(256), 0, st, dY, dYh,
                            (int64_t)c_out * P);
-        hipLaunchKernelGGL(k_wgrad<LBM_NN_BF16>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk, partial,
-                           (const short*)Xh, (const short*)dYh);
+        if (w8)
+            hipLaunchKernelGGL(k_wgrad_w8, grid, dim3(64), 0, st, (const short*)Xh, c_in, (const short*)dYh, c_out,
+                               D, H, W, chunk, partial);
+        else
+            hipLaunchKernelGGL(k_wgrad<LBM_NN_BF16>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk,
+                               partial, (const short*)Xh, (const short*)dYh);
     } else if (prec == LBM_NN_FP32) {
         hipLaunchKernelGGL(k_wgrad<LBM_NN_FP32>, grid, dim3(64), 0, st, X, c_in, dY, c_out, D, H, W, chunk, partial,
                            (const short*)nullptr, (const short*)nullptr);
