@@ -2,16 +2,18 @@
 // dense kernels (streaming with halfway bounce-back, Eq. 1-2; moments, Eq. 4
 // and 10; virtual densities at solids, Eq. 17; pseudopotential, Eq. 12;
 // interaction force, Eq. 11 and 13; BGK or MRT collision with the
-// exact-difference forcing, Eq. 3 and 5) over a list of the fluid nodes.
+// exact-difference forcing, Eq. 3 and 5; reservoir inflow by
+// anti-bounce-back, Sec. 3.4.3) over a list of the fluid nodes.
 //
 // In a sphere pack at porosity 0.35-0.4 a dense row of 64 nodes holds about
 // 25 fluid nodes, and the dense kernel reads whole cache lines of them: about
 // 2.5 times the fluid bytes, and three pulls per node (own ring pull, halo
 // pulls of the neighbouring tiles, re-pull at the collision).  Here only the
-// fluid nodes hold populations, in lattice order, and each step is two
-// passes over them:
+// fluid nodes hold populations, in lattice order, and a step is three
+// kernels, two of them passes over the fluid nodes:
 //   k_fl_rho    pull, density and psi of every fluid node;
-//   k_fl_solid  virtual density and psi of every solid node next to fluid;
+//   k_fl_solid  psi of every solid node next to fluid (virtual density) and
+//               of every reservoir node (its fixed density);
 //   k_fl_step   pull again, gather psi of the 18 neighbours, force,
 //               collision, store.
 // Both pulls read the neighbour table (ids of x - e_i), one 4-byte index per
