@@ -70,12 +70,13 @@ def test_conv_data_gradient(T, ops, cin, cout, dhw, prec, tol):
 # (16, 32, 32^3) and (8, 16, 40 x 40 x 48) take the 8- and 64-chunk paths of the
 # weight gradient (P >= 4,096 and P >= 65,536), the latter the one every
 # 64^3 and 128^3 training layer takes; (32, 128, 16^3) a 128-channel layer.
-# Rows of a multiple of 8 positions take the 16-position BF16 kernel; (3, 5,
-# 3 x 5 x 8) and (24, 40, 6 x 7 x 24) end on a half step (P not a multiple
-# of 16), the others with W of 10, 12, 4 and 6 take the general one.
+# Rows of a multiple of 8 positions take the 16-position BF16 kernel (also
+# with a single column tile, (1, 16, 4 x 4 x 16)); (3, 5, 3 x 5 x 8) and (24,
+# 40, 6 x 7 x 24) end on a half step (P not a multiple of 16); the shapes
+# with W of 10, 12, 4 and 6 take the general one.
 @pytest.mark.parametrize("cin,cout,dhw", SHAPES + [(16, 32, (32, 32, 32)), (8, 16, (40, 40, 48)),
                                                   (32, 128, (16, 16, 16)), (3, 5, (3, 5, 8)),
-                                                  (24, 40, (6, 7, 24))])
+                                                  (24, 40, (6, 7, 24)), (1, 16, (4, 4, 16))])
 @pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 2e-2)])
 def test_conv_weight_gradient(T, ops, cin, cout, dhw, prec, tol):
     from oracle import nn_ref
