@@ -235,3 +235,36 @@ def test_deviation_storage_agrees_with_dense(oracle_mod, storage):
     for c, (er, eu) in out.items():
         assert er < 5e-2 and eu < 0.5, (c, er, eu)
     assert st["nonfinite"] == 0 and st["negative"] == 0
+
+
+# ------------------------------------------------------------ degenerate cases
+def test_all_fluid_box_f64(oracle_mod):
+    # no solid node (no listed solids, no bounce-back): a periodic
+    # two-component box with a non-wetting blob
+    shape = (16, 17, 20)
+    solid = np.zeros(shape, np.uint8)
+    w, _, _ = inputs.two_component_pack(shape=shape, storage="F64", solid=solid)
+    z, y, x = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    blob = ((z - 8.0) ** 2 + (y - 8.0) ** 2 + (x - 10.0) ** 2) < 25.0
+    rho = np.stack([np.where(blob, 1.0, 0.03), np.where(blob, 0.03, 1.0)])
+    out, _, _ = run_pair(oracle_mod, fluid(w), solid, rho, 100)
+    assert_tol(out, 1e-10)
+
+
+def test_all_solid_lattice():
+    # no fluid node: steps launch nothing, moments and statistics are zero
+    import torch
+
+    from paper_2506_17713_amd import lbm
+
+    shape = (8, 9, 10)
+    solid = np.ones(shape, np.uint8)
+    w, _, _ = inputs.two_component_pack(shape=shape, storage="F32", solid=solid)
+    s = lbm.Solver(fluid(w), solid, np.ones((2,) + shape))
+    s.step(5)
+    r, u = s.moments(-1)
+    torch.cuda.synchronize()
+    assert float(r.abs().max()) == 0.0 and float(u.abs().max()) == 0.0
+    st = s.stats()
+    assert st["n_fluid"] == 0 and st["mass"][0] == 0.0 and st["nonfinite"] == 0
+    s.close()
