@@ -42,7 +42,7 @@ constexpr int NP = (Q - 1) / 2;
 // Addresses of the fluid-layout arrays (besides StepArgs).
 template <class R>
 struct FlArgs {
-    const int32_t* tab;   // [Q-1][T]: id of x - e_i (ids >= n_fl: solid; -1: solid without fluid neighbour)
+    const int32_t* tab;   // [Q-1][T]: id of x - e_i (ids >= n_fl: solid or reservoir; -1: not listed)
     const int32_t* dmap;  // [T]: lattice index of id
     const int32_t* emap;  // [N]: id of lattice node, -1 for a solid without fluid neighbour
     // per-id values with the components adjacent ([T][NC]), so that one
@@ -99,7 +99,7 @@ __device__ __forceinline__ void fl_pull(const StepArgs<typename Store<ST>::R>& P
     });
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        // a solid source (id >= n_fl, or -1) bounces back the node's own opposite population
+        // a solid or reservoir source (id >= n_fl, or -1) bounces back the node's own opposite population
         const bool bb = i != 0 && (uint32_t)src[i] >= (uint32_t)A.n_fl;
         const size_t off = bb ? (size_t)opp(i) * T + e : (size_t)i * T + (uint32_t)src[i];
         if constexpr (SS::DEV) {
