@@ -72,7 +72,7 @@ enum { LBM_WET_PHI = 0, LBM_WET_DRHO = 1 };
  * table of the 18 neighbour indices per fluid node and per solid node next to
  * fluid (porous media: at porosity 0.35 the dense rows carry about three
  * times the fluid bytes).  Same method and results as DENSE (pinned by the
- * parity tests); D3Q19 only, any storage, BGK or MRT, reservoirs but no
+ * parity tests); D3Q19 only, any storage, BGK or MRT, reservoirs and the
  * convective outlet (LBM_ERR_UNSUPPORTED otherwise), and lbm_grad is
  * LBM_ERR_UNSUPPORTED.  The state of lbm_get_state / lbm_set_state is the
  * fluid-node populations (lbm_state_bytes). */
@@ -186,8 +186,6 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes_out);
  *              plane below at time t; its density in the force gather is
  *              that of the node below it (res_rho[1] where that is solid).
  *              Not with 16-bit storage (LBM_ERR_UNSUPPORTED).
- *              The outlet is not offered with LBM_LAYOUT_FLUID
- *              (LBM_ERR_UNSUPPORTED).
  *   rho0       host double[n_comp][N], initial density per component.
  *   u0         host double[3][N] initial equilibrium velocity j/rho (x, y, z),
  *              or NULL for rest.  The velocity of Eq. 6 reported by

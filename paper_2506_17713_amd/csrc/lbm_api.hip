@@ -292,6 +292,7 @@ hipError_t conv_store(lbm_handle* h) {
 
 hipError_t run_conv(lbm_handle* h) {
     if (h->conv_plane < 0) return hipSuccess;
+    if (h->p.layout == LBM_LAYOUT_FLUID) return fluid_conv(h);
     if (h->p.lattice == LBM_D2Q9)
         return h->p.n_comp == 1 ? conv_store<LAT_D2Q9, 1>(h) : conv_store<LAT_D2Q9, 2>(h);
     return h->p.n_comp == 1 ? conv_store<LAT_D3Q19, 1>(h) : conv_store<LAT_D3Q19, 2>(h);
@@ -560,7 +561,6 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
             return LBM_ERR_ARG;
         if (is_dev(p->storage)) return LBM_ERR_UNSUPPORTED;
     }
-    if (conv_plane >= 0 && p->layout == LBM_LAYOUT_FLUID) return LBM_ERR_UNSUPPORTED;
     size_t n_solid = 0;
     for (size_t n = 0; n < N; ++n) {
         if (mask[n]) {
@@ -592,7 +592,7 @@ int lbm_init(const lbm_params* p, const uint8_t* mask, const double* rho0, const
     h->wet_uniform = wet == nullptr;
     h->has_res = has_res;
     h->conv_plane = conv_plane;
-    h->n_fl = h->n_sol = h->n_r1 = h->n_ext = h->fl_T = 0;
+    h->n_col = h->n_fl = h->n_sol = h->n_r1 = h->n_ext = h->fl_T = h->conv_lo = h->conv_hi = 0;
     std::memcpy(h->res_active, p->res_rho, sizeof(h->res_active));
     h->mostly_fluid = n_solid * 10 < N;
     // LBM_CHUNK (environment, tuning only): planes per workgroup along the

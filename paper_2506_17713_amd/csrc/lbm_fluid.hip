@@ -19,9 +19,11 @@
 // Both pulls read the neighbour table (ids of x - e_i), one 4-byte index per
 // direction and node; the gather reads psi through the same ids.
 //
-// Ids: [0, n_fl) the fluid nodes, [n_fl, n_sol) the solid nodes next to
-// fluid, [n_sol, n_r1) the nodes of reservoir 0 and [n_r1, n_ext) those of
-// reservoir 1 (open boundaries, whole planes), each range in lattice order.
+// Ids: [0, n_col) the fluid nodes, [n_col, n_fl) the nodes of a convective
+// outlet plane (pulled from like fluid, never collided), [n_fl, n_sol) the
+// solid nodes next to fluid, [n_sol, n_r1) the nodes of reservoir 0 and
+// [n_r1, n_ext) those of reservoir 1 (open boundaries, whole planes), each
+// range in lattice order.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -50,7 +52,7 @@ struct FlArgs {
     R* rho;               // [T][NC]: density of the fluid ids
     R* psi;               // [T][NC]: psi of every id
     R* U;                 // [T][NC]: U of every id (Zhang-Chen term only)
-    int n_fl, n_sol, n_r1, n_ext, T;
+    int n_col, n_fl, n_sol, n_r1, n_ext, T;
 };
 
 // Workgroup b takes ids [256 b, 256 b + 256).  The hardware deals workgroups
@@ -215,11 +217,10 @@ __global__ void __launch_bounds__(kFlThreads)
     k_fl_rho(StepArgs<typename Store<ST>::R> P, FlArgs<typename Store<ST>::R> A) {
     using R = typename Store<ST>::R;
     const int e = blockIdx.x * kFlThreads + threadIdx.x;
-    if (e >= A.n_fl) return;
+    if (e >= A.n_col) return;
     int32_t src[Q];
     R f[NC][Q];
     fl_pull<NC, ST>(P, A, e, src, f);
-    const size_t T = (size_t)A.T;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         const R r = fl_rho_sum<NC>(f, k);
@@ -300,7 +301,7 @@ __global__ void __launch_bounds__(kFlThreads)
     using S = typename Store<ST>::S;
     using R = typename Store<ST>::R;
     const int e = blockIdx.x * kFlThreads + threadIdx.x;
-    if (e >= A.n_fl) return;
+    if (e >= A.n_col) return;
     const size_t T = (size_t)A.T;
     int32_t src[Q];
     R f[NC][Q];
@@ -437,7 +438,7 @@ __global__ void __launch_bounds__(kFlThreads)
     const size_t N = (size_t)P.N;
     if (n >= P.N) return;
     const int e = A.emap[n];
-    if ((uint32_t)e >= (uint32_t)A.n_fl) {
+    if ((uint32_t)e >= (uint32_t)A.n_col) {
         if (P.mom_rho) P.mom_rho[n] = 0;
         if (P.mom_u) {
             P.mom_u[n] = 0;
@@ -479,7 +480,7 @@ __global__ void __launch_bounds__(kFlThreads)
 template <int NC, int ST>
 __global__ void __launch_bounds__(kFlThreads)
     k_fl_init(const typename Store<ST>::R* __restrict__ rho0, const typename Store<ST>::R* __restrict__ u0,
-              FlArgs<typename Store<ST>::R> A, void* fout, float* rout, int N, ResRho res) {
+              FlArgs<typename Store<ST>::R> A, void* fout, float* rout, int N, ResRho res, int NA, int NB, int NCc) {
     using SS = Store<ST>;
     using S = typename SS::S;
     using R = typename SS::R;
@@ -494,6 +495,21 @@ __global__ void __launch_bounds__(kFlThreads)
         const R eu = ex * ux + ey * uy + ez * uz;
         return (R)wi * r * ((R)1 + (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * (ux * ux + uy * uy + uz * uz));
     };
+    if (e >= A.n_col) {
+        // an outlet node holds what streams into y + e_i from it (the dense
+        // layout's initialisation of outlet nodes; full-precision storage only)
+        const int a = n % NA, b = (n / NA) % NB, c = n / (NA * NB);
+        for (int k = 0; k < NC; ++k) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const int m = (wrap_any(c + L::ec(i), NCc) * NB + wrap_any(b + L::eb(i), NB)) * NA +
+                              wrap_any(a + L::ea(i), NA);
+                const R v = feq(k, m, L::ex[i], L::ey[i], L::ez[i], L::w(i));
+                if constexpr (!SS::DEV) out[(size_t)(k * Q + i) * T + e] = (S)v;
+            });
+        }
+        return;
+    }
     for (int k = 0; k < NC; ++k) {
         const R r0 = rho0[(size_t)k * N + n];
         if constexpr (SS::DEV) rout[(size_t)e * NC + k] = (float)r0;
@@ -540,6 +556,118 @@ __global__ void __launch_bounds__(kFlThreads)
     });
 }
 
+// ---------------------------------------------------------------------------
+// Convective outlet (Sec. 3.4.2), the dense layout's outlet on fluid ids.
+// ---------------------------------------------------------------------------
+// Density and psi of the outlet ids: those of the node below (reservoir 1's
+// density where it is solid), as the dense kernels fill their rho ring.  Runs
+// after the fluid densities and before the virtual densities of the solids,
+// which average over outlet neighbours too.
+template <int NC, class R>
+__global__ void __launch_bounds__(kFlThreads) k_fl_conv_rho(StepArgs<R> P, FlArgs<R> A) {
+    const int o = A.n_col + blockIdx.x * kFlThreads + threadIdx.x;
+    if (o >= A.n_fl) return;
+    const int32_t below = A.tab[(size_t)(5 - 1) * A.T + o];  // o - e_5 = o - z
+    const bool fl = (uint32_t)below < (uint32_t)A.n_col;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const R r = fl ? A.rho[(size_t)below * NC + k] : P.res_rho[1][k];
+        R ps, u;
+        psi_of(P, k, r, ps, u);
+        A.rho[(size_t)o * NC + k] = r;
+        A.psi[(size_t)o * NC + k] = ps;
+        if (P.has_zc) A.U[(size_t)o * NC + k] = u;
+    }
+}
+
+// Partial sums (sum u_c, count) of the fluid ids [lo, hi) of the plane below
+// the outlet at time t, from this step's pulls; u_c = j_c / rho in FP64.
+template <int NC, int ST>
+__global__ void __launch_bounds__(kFlThreads)
+    k_fl_conv_u(StepArgs<typename Store<ST>::R> P, FlArgs<typename Store<ST>::R> A, int lo, int hi,
+                double* __restrict__ part) {
+    using R = typename Store<ST>::R;
+    const int e = lo + blockIdx.x * kFlThreads + threadIdx.x;
+    double u = 0.0, cnt = 0.0;
+    if (e < hi) {
+        int32_t src[Q];
+        R f[NC][Q];
+        fl_pull<NC, ST>(P, A, e, src, f);
+        double jc = 0.0, r = 0.0;
+        for (int k = 0; k < NC; ++k)
+            for (int i = 0; i < Q; ++i) {
+                r += (double)f[k][i];
+                jc += (double)f[k][i] * L::ec(i);
+            }
+        u = jc / r;
+        cnt = 1.0;
+    }
+    __shared__ double sh[2][kFlThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        u += __shfl_xor(u, off, 64);
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = u;
+        sh[1][threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double su = 0.0, sc = 0.0;
+        for (int w = 0; w < kFlThreads / 64; ++w) {
+            su += sh[0][w];
+            sc += sh[1][w];
+        }
+        part[2 * blockIdx.x] = su;
+        part[2 * blockIdx.x + 1] = sc;
+    }
+}
+
+// Ghost populations of the outlet ids after the step: for e_c(i) = -1,
+//   g_i = (f_i(x, t) + U f_i(x - c, t + 1)) / (1 + U),
+// x = o + e_i (the fluid node it streams into), f_i(x, t) = the value this
+// step pulled (fin at o), f_i(x - c, t + 1) = the population streaming into
+// the node below x (fout), U = max(0, mean u_c of the plane below).
+template <int NC, int ST>
+__global__ void __launch_bounds__(kFlThreads)
+    k_fl_conv_ghost(StepArgs<typename Store<ST>::R> P, FlArgs<typename Store<ST>::R> A,
+                    const double* __restrict__ part, int nblk) {
+    using S = typename Store<ST>::S;
+    using R = typename Store<ST>::R;
+    const int o = A.n_col + blockIdx.x * kFlThreads + threadIdx.x;
+    if (o >= A.n_fl) return;
+    double su = 0.0, sc = 0.0;  // same order in every thread: one U for the plane
+    for (int j = 0; j < nblk; ++j) {
+        su += part[2 * j];
+        sc += part[2 * j + 1];
+    }
+    double U = sc > 0.0 ? su / sc : 0.0;
+    U = U > 0.0 ? U : 0.0;
+    const size_t T = (size_t)A.T;
+    const S* fin = reinterpret_cast<const S*>(P.fin);
+    S* fout = reinterpret_cast<S*>(P.fout);
+    const int32_t src = A.tab[(size_t)(5 - 1) * T + o];  // the node below o
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (L::ec(i) == -1) {
+            const int32_t x = A.tab[(size_t)(opp(i) - 1) * T + o];  // o + e_i
+            if ((uint32_t)x >= (uint32_t)A.n_col) return;
+            const int32_t xu = A.tab[(size_t)(5 - 1) * T + x];     // the node below x
+            const bool xu_fl = (uint32_t)xu < (uint32_t)A.n_col;
+            const bool src_fl = (uint32_t)src < (uint32_t)A.n_col;
+            for (int k = 0; k < NC; ++k) {
+                const R prev = (R)fin[(size_t)(k * Q + i) * T + o];
+                R upw = prev;
+                // f_i(x - c, t + 1): from xu - e_i = the node below o, or bounced back
+                if (xu_fl) upw = src_fl ? (R)fout[(size_t)(k * Q + i) * T + src]
+                                        : (R)fout[(size_t)(k * Q + opp(i)) * T + xu];
+                fout[(size_t)(k * Q + i) * T + o] = (S)((prev + (R)U * upw) / ((R)1 + (R)U));
+            }
+        }
+    });
+}
+
 // Flag (any thread may write it) if a fluid id has an unlisted neighbour.
 __global__ void __launch_bounds__(kFlThreads)
     k_fl_check(const int32_t* __restrict__ tab, int n_fl, int T, int32_t* __restrict__ flag) {
@@ -560,6 +688,7 @@ FlArgs<R> fl_args(lbm_handle* h) {
     A.rho = reinterpret_cast<R*>(ws + h->lay.frho);
     A.psi = reinterpret_cast<R*>(ws + h->lay.fpsi);
     A.U = reinterpret_cast<R*>(ws + h->lay.fU);
+    A.n_col = h->n_col;
     A.n_fl = h->n_fl;
     A.n_sol = h->n_sol;
     A.n_r1 = h->n_r1;
@@ -575,8 +704,11 @@ template <int NC, int ST>
 hipError_t launch_psi(lbm_handle* h, const StepArgs<typename Store<ST>::R>& a,
                       const FlArgs<typename Store<ST>::R>& A) {
     using R = typename Store<ST>::R;
-    if (h->n_fl > 0)
-        hipLaunchKernelGGL((k_fl_rho<NC, ST>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream, a, A);
+    if (h->n_col > 0)
+        hipLaunchKernelGGL((k_fl_rho<NC, ST>), dim3(blocks(h->n_col)), dim3(kFlThreads), 0, h->stream, a, A);
+    if (h->n_fl > h->n_col)
+        hipLaunchKernelGGL((k_fl_conv_rho<NC, R>), dim3(blocks(h->n_fl - h->n_col)), dim3(kFlThreads), 0, h->stream,
+                           a, A);
     if (h->n_ext > h->n_fl)
         hipLaunchKernelGGL((k_fl_solid<NC, R>), dim3(blocks(h->n_ext - h->n_fl)), dim3(kFlThreads), 0, h->stream,
                            a, A);
@@ -590,12 +722,12 @@ hipError_t step_store(lbm_handle* h) {
     fill_args(h, a, nullptr);
     const FlArgs<R> A = fl_args<R>(h);
     hipError_t e = launch_psi<NC, ST>(h, a, A);
-    if (e != hipSuccess || h->n_fl == 0) return e;
+    if (e != hipSuccess || h->n_col == 0) return e;
     if (h->p.collision == LBM_MRT)
-        hipLaunchKernelGGL((k_fl_step<NC, ST, COLL_MRT>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream, a,
+        hipLaunchKernelGGL((k_fl_step<NC, ST, COLL_MRT>), dim3(blocks(h->n_col)), dim3(kFlThreads), 0, h->stream, a,
                            A);
     else
-        hipLaunchKernelGGL((k_fl_step<NC, ST, COLL_BGK>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream, a,
+        hipLaunchKernelGGL((k_fl_step<NC, ST, COLL_BGK>), dim3(blocks(h->n_col)), dim3(kFlThreads), 0, h->stream, a,
                            A);
     return hipGetLastError();
 }
@@ -623,7 +755,8 @@ hipError_t init_store(lbm_handle* h, const void* rho0, const void* u0) {
     std::memcpy(res.r, h->res_active, sizeof(res.r));
     float* rout = is_dev(h->p.storage) ? reinterpret_cast<float*>(h->ws + h->lay.rA) : nullptr;
     hipLaunchKernelGGL((k_fl_init<NC, ST>), dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream,
-                       (const R*)rho0, (const R*)u0, fl_args<R>(h), h->ws + h->lay.fA, rout, h->N, res);
+                       (const R*)rho0, (const R*)u0, fl_args<R>(h), h->ws + h->lay.fA, rout, h->N, res, h->NA, h->NB,
+                       h->NCc);
     return hipGetLastError();
 }
 
@@ -646,6 +779,26 @@ hipError_t dispatch(lbm_handle* h, Args... args) {
         default: return hipErrorInvalidValue;  // rejected at lbm_init
     }
 }
+template <int NC, int ST>
+hipError_t conv_store(lbm_handle* h) {
+    using R = typename Store<ST>::R;
+    if (h->n_fl == h->n_col || h->conv_hi <= h->conv_lo) return hipSuccess;
+    StepArgs<R> a;
+    fill_args(h, a, nullptr);
+    const FlArgs<R> A = fl_args<R>(h);
+    double* part = reinterpret_cast<double*>(h->ws + h->lay.conv_part);
+    const int nblk = blocks(h->conv_hi - h->conv_lo);
+    hipLaunchKernelGGL((k_fl_conv_u<NC, ST>), dim3(nblk), dim3(kFlThreads), 0, h->stream, a, A, h->conv_lo,
+                       h->conv_hi, part);
+    hipLaunchKernelGGL((k_fl_conv_ghost<NC, ST>), dim3(blocks(h->n_fl - h->n_col)), dim3(kFlThreads), 0, h->stream,
+                       a, A, (const double*)part, nblk);
+    return hipGetLastError();
+}
+
+template <int NC, int ST>
+struct ConvFn {
+    static hipError_t run(lbm_handle* h) { return conv_store<NC, ST>(h); }
+};
 template <int NC, int ST>
 struct StepFn {
     static hipError_t run(lbm_handle* h) { return step_store<NC, ST>(h); }
@@ -679,14 +832,28 @@ int lbmi::fluid_build(lbm_handle* h) {
         hipStreamSynchronize(h->stream) != hipSuccess)
         return LBM_ERR_HIP;
     constexpr uint32_t ALLNB = ((1u << Q) - 1u) & ~1u;
-    for (size_t n = 0; n < N; ++n)
+    // fluid ids; [conv_lo, conv_hi): those of the plane below an outlet plane
+    const size_t plane = (size_t)h->NA * h->NB;
+    const size_t ci = h->conv_plane > 0 ? (size_t)(h->conv_plane - 1) : 0;
+    h->conv_lo = h->conv_hi = 0;
+    for (size_t n = 0; n < N; ++n) {
+        if (h->conv_plane > 0 && n == ci * plane) h->conv_lo = (int)dmap.size();
+        if (h->conv_plane > 0 && n == (ci + 1) * plane) h->conv_hi = (int)dmap.size();
         if (!(word[n] & 1u)) {
+            emap[n] = (int32_t)dmap.size();
+            dmap.push_back((int32_t)n);
+        }
+    }
+    h->n_col = (int)dmap.size();
+    // outlet nodes: pulled from like fluid, so their ids are below n_fl
+    for (size_t n = 0; n < N; ++n)
+        if (word[n] & NW_OWN_CONV) {
             emap[n] = (int32_t)dmap.size();
             dmap.push_back((int32_t)n);
         }
     h->n_fl = (int)dmap.size();
     for (size_t n = 0; n < N; ++n)
-        if ((word[n] & 1u) && !(word[n] & NW_OWN_RES) && (word[n] & ALLNB) != ALLNB) {
+        if ((word[n] & 1u) && !(word[n] & (NW_OWN_RES | NW_OWN_CONV)) && (word[n] & ALLNB) != ALLNB) {
             emap[n] = (int32_t)dmap.size();
             dmap.push_back((int32_t)n);
         }
@@ -721,9 +888,9 @@ int lbmi::fluid_build(lbm_handle* h) {
     // density array, which the first step overwrites) where one is not
     int32_t* flag = reinterpret_cast<int32_t*>(ws + h->lay.frho);
     if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 4, h->stream);
-    if (e == hipSuccess && h->n_fl > 0) {
-        hipLaunchKernelGGL(k_fl_check, dim3(blocks(h->n_fl)), dim3(kFlThreads), 0, h->stream,
-                           reinterpret_cast<const int32_t*>(ws + h->lay.ftab), h->n_fl, h->fl_T, flag);
+    if (e == hipSuccess && h->n_col > 0) {
+        hipLaunchKernelGGL(k_fl_check, dim3(blocks(h->n_col)), dim3(kFlThreads), 0, h->stream,
+                           reinterpret_cast<const int32_t*>(ws + h->lay.ftab), h->n_col, h->fl_T, flag);
         e = hipGetLastError();
     }
     int32_t bad = 0;
@@ -739,6 +906,8 @@ hipError_t lbmi::fluid_init(lbm_handle* h, const void* rho0, const void* u0) {
 }
 
 hipError_t lbmi::fluid_step(lbm_handle* h) { return dispatch<StepFn>(h); }
+
+hipError_t lbmi::fluid_conv(lbm_handle* h) { return dispatch<ConvFn>(h); }
 
 hipError_t lbmi::fluid_moments(lbm_handle* h, int comp, void* rho, void* u) {
     return dispatch<MomFn>(h, comp, rho, u);

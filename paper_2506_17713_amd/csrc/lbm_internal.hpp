@@ -65,11 +65,13 @@ struct lbm_handle {
     double res_active[2][2];
     int conv_plane;    // plane of the convective outlet, -1: none
     int chunk_override;
-    // fluid-only layout: ids [0, n_fl) are the fluid nodes in lattice order,
-    // [n_fl, n_sol) the solid nodes with a fluid neighbour, [n_sol, n_r1) and
-    // [n_r1, n_ext) the nodes of reservoirs 0 and 1; fl_T is the row stride of
-    // the populations and the table (a multiple of 64)
-    int n_fl, n_sol, n_r1, n_ext, fl_T;
+    // fluid-only layout: ids [0, n_col) are the fluid nodes in lattice order,
+    // [n_col, n_fl) the convective outlet's nodes (pulled from, not
+    // collided), [n_fl, n_sol) the solid nodes with a fluid neighbour,
+    // [n_sol, n_r1) and [n_r1, n_ext) the nodes of reservoirs 0 and 1; fl_T
+    // is the row stride of the populations and the table (a multiple of 64);
+    // [conv_lo, conv_hi) the fluid ids of the plane below the outlet
+    int n_col, n_fl, n_sol, n_r1, n_ext, fl_T, conv_lo, conv_hi;
 };
 
 namespace lbmi {
@@ -85,6 +87,8 @@ int fluid_build(lbm_handle* h);
 hipError_t fluid_init(lbm_handle* h, const void* rho0, const void* u0);
 hipError_t fluid_step(lbm_handle* h);
 hipError_t fluid_moments(lbm_handle* h, int comp, void* rho, void* u);
+// Convective outlet after a step of the fluid layout (before the swap).
+hipError_t fluid_conv(lbm_handle* h);
 // Pointer to the handle's current state buffer.
 inline void* state_ptr(lbm_handle* h) { return h->ws + (h->cur ? h->lay.fB : h->lay.fA); }
 // Kernel arguments of the handle's current step (bufs: explicit buffers).

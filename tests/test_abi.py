@@ -221,8 +221,8 @@ def test_init_rejects_bad_convective_outlets(lib):
 
 
 def test_fluid_layout_validation(lib):
-    # LBM_LAYOUT_FLUID: D3Q19, BGK or MRT, no convective outlet; the
-    # workspace adds the neighbour table
+    # LBM_LAYOUT_FLUID: D3Q19, BGK or MRT; the workspace adds the neighbour
+    # table
     sz, szd = C.c_size_t(), C.c_size_t()
     assert lib.lbm_workspace_size(C.byref(_params(layout="FLUID")), C.byref(sz)) == 0
     assert lib.lbm_workspace_size(C.byref(_params()), C.byref(szd)) == 0
@@ -239,9 +239,9 @@ def test_fluid_layout_validation(lib):
     p = _params()
     p.layout = 2
     assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == -1
-    # a convective outlet: refused before the GPU is touched
+    # a convective outlet with 16-bit storage: refused before the GPU is touched
     w, mask, rho = inputs.pcsw_pack(n=12, buffer=2, shape=(18, 12, 12), outlet="convective")
-    p = lbm.params_from(w.with_(layout="FLUID"))
+    p = lbm.params_from(w.with_(layout="FLUID", storage="F16DEV"))
     assert lib.lbm_workspace_size(C.byref(p), C.byref(sz)) == 0
     m = np.ascontiguousarray(mask.reshape(-1).astype(np.uint8))
     r = np.ascontiguousarray(rho.reshape(2, -1))

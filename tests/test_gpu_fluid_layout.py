@@ -268,3 +268,46 @@ def test_all_solid_lattice():
     st = s.stats()
     assert st["n_fluid"] == 0 and st["mass"][0] == 0.0 and st["nonfinite"] == 0
     s.close()
+
+
+# --------------------------------------------------------- convective outlet
+@pytest.mark.parametrize("storage", ["F64", "F32"])
+def test_body_force_drainage_with_convective_outlet(oracle_mod, storage):
+    # Sec. 3.4.2: the non-wetting fluid of the inlet buffer driven into the
+    # wetting-saturated pack by a body force, a convective outlet at the far
+    # end (outlet ids pulled from, never collided; their ghost populations
+    # formed after each step)
+    from test_gpu_open_boundary import _RHO, check_capillary, check_fields
+
+    w, mask, rho = inputs.pcsw_pack(n=40, buffer=4, storage=storage, shape=(50, 37, 40), outlet="convective",
+                                    body=2e-4)
+    w = fluid(w.with_(name="fl_conv_drainage"))
+    _RHO[w.name] = rho
+    out, st, _ = run_pair(oracle_mod, w, mask, rho, 300)
+    check_fields(out, storage)
+    check_capillary(oracle_mod, w, mask, st, 300)
+
+
+def test_convective_outlet_agrees_with_dense():
+    # one step on both layouts from the same start (the outlet's mean
+    # velocity is summed in another order: agreement to rounding)
+    import torch
+
+    from paper_2506_17713_amd import lbm
+
+    w, mask, rho = inputs.pcsw_pack(n=24, buffer=3, storage="F64", shape=(32, 20, 24), outlet="convective",
+                                    body=2e-4)
+    d = lbm.Solver(w, mask, rho)
+    f = lbm.Solver(fluid(w), mask, rho)
+    for steps in (1, 49):
+        d.step(steps)
+        f.step(steps)
+        rd, ud = d.moments(-1)
+        rf, uf = f.moments(-1)
+        torch.cuda.synchronize()
+        er = float((rd - rf).abs().max() / rd.abs().max())
+        eu = float((ud - uf).abs().max() / ud.abs().max())
+        print(f"outlet layouts after {d.stats()['step']} steps: rho {er:.3g} u {eu:.3g}", flush=True)
+        assert er <= 1e-12 and eu <= 1e-10
+    d.close()
+    f.close()
