@@ -398,8 +398,8 @@ def main():
     if args.steps is None:
         args.steps = {"adjoint": 1000, "surrogate": 20}.get(args.workload, 500)
     if args.gpus != 1:
-        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU x-slab sharding is "
-                                   "described in DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this library runs on one GPU only; sharding over GPUs (x-slabs with a "
+                                   "face exchange over RCCL) is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
